@@ -1,0 +1,192 @@
+"""Benchmark: CG-SENSE on one MI355X, reported as E^H E applies per second.
+
+Workload (default): 160 independent 2D slices of 256x256 with 12 coils and
+their own sensitivity maps, variable-density mask R=4 with 24 centre lines,
+30 CG iterations per solve, complex64 storage with fp64 inner products.
+One step = one full solve of the batch (E^H y, CG init, 30 x [fused E^H E
+with the p update, x/r update], finish).  Inputs are seeded synthetic
+phantoms, coil maps, mask and noise, resident in HBM before timing.
+
+Prints one JSON line with the metric, the roofline of the dominant kernel
+(the fused E^H E launch, timed with HIP events on its stream inside the
+timed region) and the FP64 oracle timed on the host for a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=160)
+    ap.add_argument("--iters", type=int, default=30)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--maps-storage", default="c64", choices=["c64", "bf16", "fp16"])
+    return ap.parse_args()
+
+
+def make_inputs(w, B, dev):
+    import torch
+
+    from paper_1807_11830_amd import synth
+
+    n, C = w.n, w.ncoils
+    mask = w.mask_array()
+    # per-slice maps: 16 distinct rotations, cycled over the batch (every
+    # slice still owns its own buffer in HBM)
+    uniq = min(B, 16)
+    maps_u = np.stack([synth.coil_maps2d(n, C, rotation=2.0 * np.pi * i / (uniq * C))
+                       for i in range(uniq)]).astype(np.complex64)
+    maps = torch.empty((B, C, n, n), dtype=torch.complex64, device=dev)
+    mu = torch.from_numpy(maps_u).to(dev)
+    for b in range(B):
+        maps[b].copy_(mu[b % uniq])
+    imgs = torch.from_numpy(np.stack([synth.phantom2d(n, seed=synth.SEED_PHANTOM + b)
+                                      for b in range(B)]).astype(np.complex64)).to(dev)
+    return maps, imgs, mask, maps_u[0]
+
+
+def cpu_baseline(w, maps0, mask, y0, target_s):
+    """FP64 oracle CG on one slice of the workload, iterations bounded so the
+    sample takes about target_s seconds.  Returns applies/s and the sample."""
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    maps0 = maps0.astype(np.complex128)
+    y0 = y0.astype(np.complex128)[None]
+    t0 = time.perf_counter()
+    oracle.A(oracle.EH(y0, maps0, mask), maps0, mask)
+    t_a = time.perf_counter() - t0
+    k = int(max(1, min(w.iters, round(target_s / max(t_a, 1e-3)))))
+    t0 = time.perf_counter()
+    oracle.cg(y0, maps0, mask, k)
+    dt = time.perf_counter() - t0
+    return dict(value=k / dt, unit="applies/s", cores=min(threads, w.ncoils), kind="oracle",
+                sample=f"1 slice {w.n}x{w.n}, {w.ncoils} coils: E^H y + {k} CG iterations "
+                       f"(E^H E composed as E^H(E p), fp64, {min(threads, w.ncoils)} OpenMP threads "
+                       f"over coils) in {dt:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(slices are independent: shard the batch across processes instead)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1807_11830_amd import sense, synth
+
+    w = synth.SLICE_256
+    B, K = args.batch, args.iters
+    dev = torch.device("cuda:0")
+    log(f"bench: building inputs ({B} slices {w.n}x{w.n}, {w.ncoils} coils)")
+    maps, imgs, mask, maps0 = make_inputs(w, B, dev)
+    plan = sense.Plan(maps, mask, batch=B, maps_storage=args.maps_storage)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.SEED_NOISE)
+    y = plan.E(imgs)
+    noise = 1e-3 * torch.complex(torch.randn(y.shape, generator=gen, device=dev),
+                                 torch.randn(y.shape, generator=gen, device=dev))
+    y += noise * torch.from_numpy(mask.astype(np.float32)).to(dev)[None, None, :, None]
+    x = torch.empty_like(imgs)
+    torch.cuda.synchronize()
+    del noise
+
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        plan.cg(y, K, out=x, sync=False)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    log(f"bench: timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.cg(y, K, out=x, sync=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_l, ms_l = plan.profile()
+    plan.set_profiling(False)
+    res = plan.cg(y, K, out=x)
+    assert int(res.iters.min()) == K, res.iters
+
+    nvox = w.n * w.n
+    C = w.ncoils
+    avg_s = ms_l / 1e3 / max(n_l, 1)
+    # fused CG launch: reads S (C values), r and p_old, writes p and q
+    sbytes = 8 if args.maps_storage == "c64" else 4
+    bytes_launch = B * nvox * (sbytes * C + 8 * 4)
+    achieved = bytes_launch / avg_s / 1e9
+    applies = B * K * args.steps
+    log(f"bench: {dt * 1e3 / args.steps:.2f} ms/step, fused launch avg {avg_s * 1e6:.1f} us "
+        f"({achieved:.0f} GB/s)")
+
+    # the metric's unit alone: standalone E^H E apply, (C+2) complex vectors
+    plan.set_profiling(True)
+    p = imgs
+    q = torch.empty_like(p)
+    for _ in range(20):
+        plan.EHE(p, out=q)
+    torch.cuda.synchronize()
+    n_a, ms_a = plan.profile()
+    plan.set_profiling(False)
+    apply_s = ms_a / 1e3 / max(n_a, 1)
+    apply_bytes = B * nvox * (sbytes * C + 16)
+    log(f"bench: standalone apply {apply_s * 1e6:.1f} us ({apply_bytes / apply_s / 1e9:.0f} GB/s)")
+
+    out = {
+        "metric": "E^H E applies/s (CG-SENSE, 256x256, 12 coils, R=4, 30 iterations)",
+        "value": applies / dt,
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "slices": B, "iters": K, "maps": "per-slice",
+                   "maps_storage": args.maps_storage, "kspace_storage": "c64",
+                   "inner_products": "f64", "nx": w.n, "ny": w.n, "coils": C},
+        "roofline": {"bound": "hbm", "kernel": "ehe2d_kernel (fused E^H E + p update, CG mode)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": avg_s * 1e6, "launches": n_l,
+                     "bytes_per_launch": bytes_launch},
+        "ehe_apply": {"avg_launch_us": apply_s * 1e6, "bytes_per_launch": apply_bytes,
+                      "achieved_gbs": apply_bytes / apply_s / 1e9,
+                      "applies_per_s": B / apply_s},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        y0 = y[0].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(w, maps0, mask, y0, args.cpu_seconds)
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

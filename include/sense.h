@@ -1,0 +1,196 @@
+/*
+ * sense.h - C ABI of the MI355X (gfx950) CG-SENSE library.
+ *
+ * Multicoil Cartesian MRI encoding on one GPU:
+ *
+ *   E     y_c = M .* F(S_c .* x)                  forward model, per coil c
+ *   E^H   x   = sum_c conj(S_c) .* F^H(M .* y_c)   adjoint
+ *   A     q   = E^H E p + lambda p                 normal operator
+ *   CG    conjugate gradients on A x = E^H y from x = 0 (CG-SENSE)
+ *
+ * F is the centred unitary DFT over the image axes (x = readout, y and z =
+ * phase encodes): F = n^(-1/2) fftshift . DFT . ifftshift per axis, with the
+ * forward direction exp(-2 pi i k n / N) taking images to k-space.  M is a
+ * binary sampling mask over the phase-encode axes that broadcasts along x.
+ * With M = 1, E^H is the reconstruction equation of the paper (arXiv
+ * 1807.11830, Section "Sensitivity-weighted multicoil image reconstruction",
+ * Eq. (1)): inverse transform of each coil image, product with the conjugate
+ * sensitivity map, sum over the coils of a frame; the unitary inverse here
+ * carries n^(-1/2) where an unscaled inverse DFT with 1/n would carry 1/n.
+ *
+ * Operator model (Section "Algorithm handling" and the discussion after the
+ * reconstruction listings): every operation has inputs, outputs and
+ * parameters, and its once-only initialisation (here: plan creation, which
+ * validates sizes, builds twiddle and mask tables and allocates workspace)
+ * is split from the launch (the apply calls, which only enqueue kernels).
+ * Chained operations pass device buffers without copies.
+ *
+ * Conventions that hold for every call:
+ *  - Layouts are row-major with x fastest, complex values interleaved
+ *    (re, im):  x [B][Nz][Ny][Nx],  y [B][C][Nz][Ny][Nx],
+ *    maps [B or 1][C][Nz][Ny][Nx]; 2D problems have Nz = 1 and ndim = 2.
+ *  - complex64 = two float32; SENSE_BF16X2 / SENSE_FP16X2 = two 16-bit
+ *    values (re at the lower address).  x, p, q are always complex64.
+ *  - Pointers named d_* are device pointers on the plan's device, owned by
+ *    the caller.  Pointers named h_* are host memory.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    Apply and solve calls are asynchronous: they enqueue work on the
+ *    stream and return; results are valid once the stream is synchronised.
+ *    They never allocate memory.
+ *  - Errors: every call returns a sense_status; on failure nothing is
+ *    enqueued and sense_last_error() returns a message for the calling
+ *    thread.  No C++ exception crosses this boundary.
+ */
+#ifndef SENSE_H
+#define SENSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define SENSE_API __attribute__((visibility("default")))
+#else
+#define SENSE_API
+#endif
+
+typedef struct sense_plan_s* sense_plan;
+
+typedef enum {
+  SENSE_OK = 0,
+  SENSE_ERR_INVALID = 1,     /* bad argument: null pointer, bad size, aliasing */
+  SENSE_ERR_UNSUPPORTED = 2, /* valid request outside what the library implements */
+  SENSE_ERR_NOMEM = 3,       /* device allocation failed at plan creation */
+  SENSE_ERR_DEVICE = 4,      /* a HIP runtime call or kernel launch failed */
+  SENSE_ERR_STATE = 5        /* call not allowed in the plan's current state */
+} sense_status;
+
+typedef enum {
+  SENSE_C64 = 0,    /* complex64: float32 re, float32 im */
+  SENSE_BF16X2 = 1, /* bfloat16 re, bfloat16 im; converted to fp32 on load, RNE on store */
+  SENSE_FP16X2 = 2  /* float16 re, float16 im; converted to fp32 on load, RNE on store */
+} sense_storage;
+
+/* CG stop reasons, one per batch element. */
+typedef enum {
+  SENSE_CG_MAXITER = 0,   /* ran max_iter iterations */
+  SENSE_CG_CONVERGED = 1, /* sqrt(rho_k / rho_0) < rel_tol after an update */
+  SENSE_CG_EXACT = 2,     /* rho_k == 0 at the start of an iteration */
+  SENSE_CG_BREAKDOWN = 3, /* Re<p, A p> <= 0 */
+  SENSE_CG_NONFINITE = 4  /* a reduction produced Inf or NaN */
+} sense_cg_status;
+
+typedef struct {
+  int32_t ndim;           /* 2 or 3 */
+  int64_t nx, ny, nz;     /* image size; nz = 1 when ndim = 2 */
+  int32_t ncoils;         /* C >= 1 */
+  int32_t batch;          /* B >= 1 independent problems */
+  int32_t maps_storage;   /* sense_storage of the sensitivity maps */
+  int32_t kspace_storage; /* sense_storage of k-space y */
+  int32_t maps_shared;    /* 1: one [C][...] map set serves every batch element */
+} sense_desc;
+
+/* Per batch element result of sense_cg_solve (24 bytes). */
+typedef struct {
+  int32_t iters_run; /* completed updates of x */
+  int32_t status;    /* sense_cg_status */
+  double rho0;       /* <b, b>, b = E^H y */
+  double rho_final;  /* <r, r> when the loop stopped */
+} sense_cg_info;
+
+/*
+ * Device bytes a plan for this descriptor allocates (tables, workspace and
+ * CG vectors), so a scheduler can admit work by memory footprint.  Returns 0
+ * for an invalid or unsupported descriptor.
+ */
+SENSE_API size_t sense_plan_device_bytes(const sense_desc* desc);
+
+/*
+ * Create a plan on the current HIP device (the paper's init step).
+ *   desc    sizes and storage formats (copied).
+ *   d_maps  sensitivity maps in desc->maps_storage, layout as above.  The plan
+ *           borrows the pointer: the buffer must stay valid and unchanged
+ *           while the plan is used.
+ *   h_mask  uint8 host array of Nz*Ny entries in centred order ([Nz][Ny],
+ *           DC at index (Nz/2, Ny/2)); nonzero = sampled.  Copied.
+ *   stream  stream used for the table uploads (synchronised before return).
+ *   out     receives the plan.
+ * Supported: ndim = 2 (3 reported UNSUPPORTED for now); Ny and Nx from
+ * {8, 16, 32, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384}; the normal
+ * operator alone accepts any Nx >= 1.  Other sizes -> SENSE_ERR_UNSUPPORTED.
+ */
+SENSE_API sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const uint8_t* h_mask,
+                               void* stream, sense_plan* out);
+
+/* Release a plan and its device memory (synchronises the device first). */
+SENSE_API sense_status sense_plan_destroy(sense_plan plan);
+
+/*
+ * Forward operator: d_y[B][C][Nz][Ny][Nx] (kspace_storage) = E d_x.
+ * Unsampled locations are written as zeros.  d_x complex64 [B][...].
+ * d_x and d_y must not overlap.
+ */
+SENSE_API sense_status sense_apply_E(sense_plan plan, const void* d_x, void* d_y, void* stream);
+
+/*
+ * Adjoint operator: d_x[B][...] (complex64) = E^H d_y.  The mask is applied
+ * to d_y again, so values of d_y at unsampled locations are ignored, and
+ * d_y is never modified.  d_x and d_y must not overlap.
+ */
+SENSE_API sense_status sense_apply_EH(sense_plan plan, const void* d_y, void* d_x, void* stream);
+
+/*
+ * Normal operator: d_q = E^H E d_p + lambda d_p, complex64 [B][...].
+ * Computed in one fused pass per column (readout transforms cancel).
+ * d_p and d_q must not overlap.
+ */
+SENSE_API sense_status sense_apply_EHE(sense_plan plan, const void* d_p, void* d_q, double lambda,
+                             void* stream);
+
+/*
+ * CG-SENSE on (E^H E + lambda I) x = E^H y, one independent problem per
+ * batch element, starting from x = 0.  Per iteration: q = A p,
+ * alpha = rho / Re<p, q>, x += alpha p, r -= alpha q, rho' = <r, r>,
+ * beta = rho' / rho, p = r + beta p.  Inner products, alpha and beta are
+ * fp64 and stay on the device; vectors are complex64.
+ *   d_y        k-space [B][C][...] in kspace_storage.
+ *   d_x        output image [B][...] complex64 (must not overlap d_y).
+ *   max_iter   >= 0 iterations at most.
+ *   rel_tol    stop when sqrt(rho'/rho_0) < rel_tol (0 disables).
+ *   lambda     Tikhonov weight (0 = plain CG-SENSE).
+ *   d_info     optional device array of B sense_cg_info (NULL = skip); the
+ *              plan also keeps the last result for sense_plan_cg_info.
+ *   d_rho_hist optional device array [B][max_iter + 1] of fp64 rho_k
+ *              (entries past the stop iteration are left untouched).
+ */
+SENSE_API sense_status sense_cg_solve(sense_plan plan, const void* d_y, void* d_x, int32_t max_iter,
+                            double rel_tol, double lambda, sense_cg_info* d_info,
+                            double* d_rho_hist, void* stream);
+
+/* Copy the last sense_cg_solve result of every batch element to host memory
+ * h_info[B]; synchronises the stream. */
+SENSE_API sense_status sense_plan_cg_info(sense_plan plan, sense_cg_info* h_info, void* stream);
+
+/*
+ * Stage timing (the paper's per-launch profile parameters).  When enabled,
+ * every fused E^H E launch is bracketed by HIP events on its stream; after
+ * the stream is synchronised sense_plan_profile returns the number of timed
+ * launches and their total duration in milliseconds, then clears the record.
+ */
+SENSE_API sense_status sense_plan_set_profiling(sense_plan plan, int32_t enable);
+SENSE_API sense_status sense_plan_profile(sense_plan plan, int64_t* n_launches, double* total_ms);
+
+/* Message of the last failed call on this thread ("" if none). */
+SENSE_API const char* sense_last_error(void);
+
+/* Library version string. */
+SENSE_API const char* sense_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SENSE_H */

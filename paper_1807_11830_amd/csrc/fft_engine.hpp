@@ -1,0 +1,102 @@
+// Stockham FFT of one line of length N held by T cooperating threads.
+//
+// Register layout: thread t (0 <= t < T) holds the E = N/T elements at line
+// positions t + T*j, j = 0..E-1, in v[j].  A radix-R Stockham stage with
+// span NS (product of the radices already done) treats butterfly jb as the
+// elements jb + r*(N/R), r < R; thread t owns butterflies jb = t + T*m,
+// m < E/R, whose inputs are exactly its own registers v[m + r*E/R] whenever
+// R divides E.  The stage multiplies input r by W_(NS*R)^(r * (jb mod NS)),
+// takes the radix-R DFT and writes output r to position
+//     (jb / NS) * NS * R + (jb mod NS) + r * NS.
+// After the last stage (NS * R = N) that position is t + T*(m + r*E/R): the
+// thread's own register again, so transforms start and end in the same
+// layout and no reordering pass is ever needed.  Between two stages the
+// block exchanges through LDS (one barrier per exchange; two buffers are
+// alternated so the next write never races the previous read).
+//
+// The inverse transform (DIR = +1) runs the same stages with conjugated
+// twiddles, so a forward/inverse pair returns every value to the thread and
+// register that held it.
+#pragma once
+
+#include "dft_small.hpp"
+
+namespace sense {
+
+template <int... Rs>
+struct Radices {
+  static constexpr int count = sizeof...(Rs);
+};
+
+template <int... Rs>
+constexpr int radix_product(Radices<Rs...>) {
+  return (1 * ... * Rs);
+}
+
+// LDS view for one line: element at position p sits at base[p * PS].
+template <int PS>
+struct LineView {
+  c32* base;
+  __device__ __forceinline__ c32& at(int p) const { return base[p * PS]; }
+};
+
+// One Stockham stage.  tw[e] = exp(-2 pi i e / N), e < N (fp32 from fp64).
+template <int N, int T, int R, int NS, int DIR, bool LAST, class View>
+__device__ __forceinline__ void stockham_stage(c32* v, int t, const c32* __restrict__ tw,
+                                               View out) {
+  constexpr int E = N / T;
+  constexpr int M = E / R;
+  static_assert(E % R == 0, "each radix must divide the elements per thread");
+  sfor<M>([&](auto mc) {
+    constexpr int m = decltype(mc)::value;
+    c32 a[R];
+    sfor<R>([&](auto rc) { a[decltype(rc)::value] = v[m + decltype(rc)::value * M]; });
+    const int jb = t + T * m;
+    const int jm = jb % NS;
+    if constexpr (NS > 1) {
+      constexpr int step = N / (NS * R);
+      sfor<R - 1>([&](auto rc) {
+        constexpr int r = decltype(rc)::value + 1;
+        const c32 w = tw[jm * (r * step)];
+        a[r] = (DIR < 0) ? cmul(a[r], w) : cmulc(a[r], w);
+      });
+    }
+    DFT<R, DIR>::run(a);
+    if constexpr (LAST) {
+      sfor<R>([&](auto rc) { v[m + decltype(rc)::value * M] = a[decltype(rc)::value]; });
+    } else {
+      const int base = (jb / NS) * (NS * R) + jm;
+      sfor<R>([&](auto rc) { out.at(base + decltype(rc)::value * NS) = a[decltype(rc)::value]; });
+    }
+  });
+}
+
+// Recursive driver over the radix list.  BUF selects the LDS buffer of the
+// next exchange.
+template <int N, int T, int DIR, int NS, int BUF, class View, int R, int... Rest>
+__device__ __forceinline__ void fft_stages(c32* v, int t, const c32* tw, View b0, View b1) {
+  constexpr bool last = sizeof...(Rest) == 0;
+  const View& out = (BUF == 0) ? b0 : b1;
+  stockham_stage<N, T, R, NS, DIR, last>(v, t, tw, out);
+  if constexpr (!last) {
+    __syncthreads();
+    constexpr int E = N / T;
+    sfor<E>([&](auto jc) { v[decltype(jc)::value] = out.at(t + T * decltype(jc)::value); });
+    fft_stages<N, T, DIR, NS * R, BUF ^ 1, View, Rest...>(v, t, tw, b0, b1);
+  }
+}
+
+template <int N, int T, int DIR, int BUF, class View, int... Rs>
+__device__ __forceinline__ void fft_line(c32* v, int t, const c32* tw, View b0, View b1,
+                                         Radices<Rs...>) {
+  static_assert(radix_product(Radices<Rs...>{}) == N, "radices must multiply to N");
+  fft_stages<N, T, DIR, 1, BUF, View, Rs...>(v, t, tw, b0, b1);
+}
+
+// Number of LDS exchanges of one transform.
+template <int... Rs>
+constexpr int exchanges(Radices<Rs...>) {
+  return (int)sizeof...(Rs) - 1;
+}
+
+}  // namespace sense

@@ -1,0 +1,101 @@
+// Internal interface between the host runtime (plan.hip) and the kernel
+// launchers (kernels_*.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cplx.hpp"
+
+namespace sense {
+
+// Per-batch-element CG state, device resident.  rho[k & 1] holds rho_k, so
+// a kernel of iteration k can read rho_(k-1) while the designated block of
+// the same launch publishes rho_k.
+// rho_cur is rho_k of the current iteration, published by the fused E^H E
+// launch for the update launch that follows it.
+struct CgState {
+  int32_t iter;     // completed updates of x; advanced by the update launch
+  int32_t status;   // CG_RUNNING while the loop goes on
+  int32_t pad0, pad1;
+  double rho0;
+  double rho[2];
+  double rho_cur;
+};
+
+enum : int32_t {
+  CG_MAXITER = 0,
+  CG_CONVERGED = 1,
+  CG_EXACT = 2,
+  CG_BREAKDOWN = 3,
+  CG_NONFINITE = 4,
+  CG_RUNNING = -1
+};
+
+// Matches the public sense_cg_info layout.
+struct CgInfo {
+  int32_t iters_run;
+  int32_t status;
+  double rho0;
+  double rho_final;
+};
+
+// Geometry of one operator instance (2D: nz = 1).
+struct Geom {
+  long nx, ny, nz;
+  int ncoils;
+  int batch;
+  long maps_bstride;  // elements between batch elements of the maps (0 = shared)
+  int maps_storage;   // Storage
+  int kspace_storage; // Storage
+};
+
+// Device tables owned by the plan.
+struct Tables {
+  const c32* tw_x;        // exp(-2 pi i e / nx), e < nx
+  const c32* tw_y;        // exp(-2 pi i e / ny)
+  const c32* tw_z;        // exp(-2 pi i e / nz)
+  const float* mu_y;      // 2D hybrid: uncentred mask / ny, [ny]
+  const uint8_t* mask_c;  // centred mask [nz][ny]
+  const int32_t* rows_s;  // sampled row ids z*ny + y
+  int n_rows_s;
+  const int32_t* rows_u;  // unsampled row ids
+  int n_rows_u;
+};
+
+struct CgArgs {
+  CgState* state;        // [B]
+  double* eta_part;      // [B][eta_tiles]
+  double* rr_part;       // [B][rr_tiles]
+  int eta_tiles;
+  int rr_tiles;
+  double* rho_hist;      // optional [B][hist_len]
+  int hist_len;
+  double tol;
+};
+
+// Supported transform lengths (compile-time instantiations).
+bool length_supported(long n);
+// Tiles of the fused E^H E kernel along x for a given ny.
+int ehe_tile_width(long ny);
+// Tiles of the CG vector kernels per batch element.
+int cg_tiles(long nvox);
+
+// Launchers; return hipSuccess or the launch error.
+hipError_t launch_ehe(const Geom& g, const Tables& tb, const void* maps, const c32* p, c32* q,
+                      float lambda, double* eta_part, hipStream_t st);
+hipError_t launch_ehe_cg(const Geom& g, const Tables& tb, const void* maps, const c32* r, c32* p,
+                         c32* q, float lambda, const CgArgs& cg, hipStream_t st);
+hipError_t launch_cg_init(const Geom& g, const c32* b, c32* x, c32* r, c32* p,
+                          const CgArgs& cg, hipStream_t st);
+hipError_t launch_cg_update(const Geom& g, c32* x, c32* r, const c32* p, const c32* q,
+                            const CgArgs& cg, hipStream_t st);
+hipError_t launch_cg_finish(const Geom& g, const CgArgs& cg, CgInfo* info, hipStream_t st);
+
+// Full-grid forward and adjoint operators (2D).
+hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32* x, c32* work,
+                    void* y, hipStream_t st);
+hipError_t launch_EH(const Geom& g, const Tables& tb, const void* maps, const void* y, c32* work,
+                     c32* x, hipStream_t st);
+
+}  // namespace sense

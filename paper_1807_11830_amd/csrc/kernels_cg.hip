@@ -1,0 +1,164 @@
+// Conjugate-gradient vector kernels for CG-SENSE (the normal equations
+// E^H E x = E^H y), one independent problem per batch element.
+//
+//   init    x = 0, p = r (= b = E^H y), partial <r, r>;  state reset
+//   update  alpha = rho_k / eta with eta = Re<p, q> summed from the fused
+//           E^H E partials; x += alpha p, r -= alpha q, partial <r, r>
+//   finish  final tolerance test and per-problem info
+//
+// The fused E^H E launch of the next iteration sums the <r, r> partials
+// itself and forms p = r + beta p.  Inner products, alpha and beta are fp64;
+// vectors are fp32 complex.  Every block of a batch element reduces the same
+// partials in the same order, so all blocks take the same decisions and the
+// results do not depend on scheduling.
+#include "kernels.hpp"
+#include "reduce.hpp"
+
+namespace sense {
+
+constexpr int CG_NT = 256;      // threads per block
+constexpr int CG_VEC = 2;       // complex values per 16-byte access
+constexpr int CG_STEPS = 4;     // accesses per thread per block
+constexpr int CG_CHUNK = CG_NT * CG_VEC * CG_STEPS;  // complex values per block
+
+int cg_tiles(long nvox) { return (int)((nvox + CG_CHUNK - 1) / CG_CHUNK); }
+
+struct alignas(16) c32x2 {
+  c32 a, b;
+};
+
+__global__ void __launch_bounds__(CG_NT) cg_init_kernel(const c32* __restrict__ bvec, c32* __restrict__ x,
+                                                        c32* __restrict__ r, c32* __restrict__ p,
+                                                        long nvox, CgArgs cg) {
+  __shared__ double red[CG_NT / 64];
+  const int b = blockIdx.y;
+  const long base = (long)b * nvox + (long)blockIdx.x * CG_CHUNK;
+  const long lim = (long)b * nvox + nvox;
+  double acc = 0.0;
+#pragma unroll
+  for (int s = 0; s < CG_STEPS; ++s) {
+    const long i = base + ((long)s * CG_NT + threadIdx.x) * CG_VEC;
+    if (i < lim) {  // nvox is even, so a pair never straddles the end
+      c32x2 v = *reinterpret_cast<const c32x2*>(bvec + i);
+      if (r != bvec) *reinterpret_cast<c32x2*>(r + i) = v;
+      *reinterpret_cast<c32x2*>(p + i) = v;
+      *reinterpret_cast<c32x2*>(x + i) = c32x2{{0.f, 0.f}, {0.f, 0.f}};
+      acc += (double)v.a.re * v.a.re + (double)v.a.im * v.a.im + (double)v.b.re * v.b.re +
+             (double)v.b.im * v.b.im;
+    }
+  }
+  const double tot = block_sum<CG_NT>(acc, red);
+  if (threadIdx.x == 0) {
+    cg.rr_part[(long)b * cg.rr_tiles + blockIdx.x] = tot;
+    if (blockIdx.x == 0) {
+      CgState s{};
+      s.iter = 0;
+      s.status = CG_RUNNING;
+      cg.state[b] = s;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(CG_NT) cg_update_kernel(c32* __restrict__ x, c32* __restrict__ r,
+                                                          const c32* __restrict__ p,
+                                                          const c32* __restrict__ q, long nvox,
+                                                          CgArgs cg) {
+  __shared__ double red[CG_NT / 64];
+  const int b = blockIdx.y;
+  CgState* st = cg.state + b;
+  if (st->status != CG_RUNNING) return;
+  const double eta = ordered_sum(cg.eta_part + (long)b * cg.eta_tiles, cg.eta_tiles);
+  int stop = CG_RUNNING;
+  if (!finite64(eta)) stop = CG_NONFINITE;
+  else if (eta <= 0.0) stop = CG_BREAKDOWN;
+  if (stop != CG_RUNNING) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->status = stop;
+    return;
+  }
+  const double alpha = st->rho_cur / eta;
+
+  const long base = (long)b * nvox + (long)blockIdx.x * CG_CHUNK;
+  const long lim = (long)b * nvox + nvox;
+  double acc = 0.0;
+#pragma unroll
+  for (int s = 0; s < CG_STEPS; ++s) {
+    const long i = base + ((long)s * CG_NT + threadIdx.x) * CG_VEC;
+    if (i < lim) {
+      c32x2 xv = *reinterpret_cast<const c32x2*>(x + i);
+      c32x2 rv = *reinterpret_cast<const c32x2*>(r + i);
+      const c32x2 pv = *reinterpret_cast<const c32x2*>(p + i);
+      const c32x2 qv = *reinterpret_cast<const c32x2*>(q + i);
+      xv.a.re = (float)((double)xv.a.re + alpha * pv.a.re);
+      xv.a.im = (float)((double)xv.a.im + alpha * pv.a.im);
+      xv.b.re = (float)((double)xv.b.re + alpha * pv.b.re);
+      xv.b.im = (float)((double)xv.b.im + alpha * pv.b.im);
+      rv.a.re = (float)((double)rv.a.re - alpha * qv.a.re);
+      rv.a.im = (float)((double)rv.a.im - alpha * qv.a.im);
+      rv.b.re = (float)((double)rv.b.re - alpha * qv.b.re);
+      rv.b.im = (float)((double)rv.b.im - alpha * qv.b.im);
+      *reinterpret_cast<c32x2*>(x + i) = xv;
+      *reinterpret_cast<c32x2*>(r + i) = rv;
+      acc += (double)rv.a.re * rv.a.re + (double)rv.a.im * rv.a.im + (double)rv.b.re * rv.b.re +
+             (double)rv.b.im * rv.b.im;
+    }
+  }
+  const double tot = block_sum<CG_NT>(acc, red);
+  if (threadIdx.x == 0) {
+    cg.rr_part[(long)b * cg.rr_tiles + blockIdx.x] = tot;
+    if (blockIdx.x == 0) st->iter = st->iter + 1;
+  }
+}
+
+__global__ void cg_finish_kernel(CgArgs cg, CgInfo* info) {
+  const int b = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  CgState* st = cg.state + b;
+  const int k = st->iter;
+  int status = st->status;
+  double rho0 = st->rho0;
+  double rho_final;
+  if (status == CG_RUNNING) {
+    const double rho = ordered_sum(cg.rr_part + (long)b * cg.rr_tiles, cg.rr_tiles);
+    if (k == 0) rho0 = rho;
+    if (cg.rho_hist && k < cg.hist_len) cg.rho_hist[(long)b * cg.hist_len + k] = rho;
+    if (!finite64(rho)) status = CG_NONFINITE;
+    else if (k > 0 && cg.tol > 0.0 && sqrt(rho / rho0) < cg.tol) status = CG_CONVERGED;
+    else status = CG_MAXITER;
+    st->status = status;
+    st->rho0 = rho0;
+    rho_final = rho;
+  } else {
+    rho_final = st->rho[k & 1];
+  }
+  if (info) {
+    CgInfo o;
+    o.iters_run = k;
+    o.status = status;
+    o.rho0 = rho0;
+    o.rho_final = rho_final;
+    info[b] = o;
+  }
+}
+
+hipError_t launch_cg_init(const Geom& g, const c32* bvec, c32* x, c32* r, c32* p, const CgArgs& cg,
+                          hipStream_t st) {
+  const long nvox = g.nx * g.ny * g.nz;
+  dim3 grid((unsigned)cg_tiles(nvox), (unsigned)g.batch);
+  hipLaunchKernelGGL(cg_init_kernel, grid, dim3(CG_NT), 0, st, bvec, x, r, p, nvox, cg);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const Geom& g, c32* x, c32* r, const c32* p, const c32* q,
+                            const CgArgs& cg, hipStream_t st) {
+  const long nvox = g.nx * g.ny * g.nz;
+  dim3 grid((unsigned)cg_tiles(nvox), (unsigned)g.batch);
+  hipLaunchKernelGGL(cg_update_kernel, grid, dim3(CG_NT), 0, st, x, r, p, q, nvox, cg);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_finish(const Geom& g, const CgArgs& cg, CgInfo* info, hipStream_t st) {
+  hipLaunchKernelGGL(cg_finish_kernel, dim3((unsigned)g.batch), dim3(64), 0, st, cg, info);
+  return hipGetLastError();
+}
+
+}  // namespace sense

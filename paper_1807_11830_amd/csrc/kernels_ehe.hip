@@ -1,0 +1,220 @@
+// Fused normal operator q = E^H E p + lambda p for 2D Cartesian SENSE.
+//
+// With a mask that depends on ky only, the centred 2D transforms factor as
+// F = F_x (x) F_y and F^H diag(M) F = I_x (x) (F_y^H diag(M_y) F_y).  For even
+// Ny the centring shifts are circular shifts by Ny/2, which commute with the
+// circulant F_y^H diag(M_y) F_y, so
+//     F_y^H diag(M_y) F_y = DFT^-1 diag(M_u / Ny) DFT,  M_u[k] = M_y[(k+Ny/2) mod Ny]
+// (DFT unnormalised, DFT^-1 its conjugate transpose).  Hence
+//     q[:, x] = sum_c conj(S_c[:, x]) * DFT^-1( (M_u/Ny) * DFT( S_c[:, x] * p[:, x] ) )
+// for every readout column x independently: only length-Ny transforms along
+// y, no readout transform and no centring signs.  This is the coil product
+// and conjugate-sensitivity coil sum of the paper's reconstruction equation
+// (Eq. (1)) around a masked forward/inverse transform pair.
+//
+// One block owns TX adjacent columns of one batch element (coalesced rows of
+// TX complex values) and loops over the coils; p, the coil's S column
+// segment and the accumulator q stay in registers, and the forward/inverse
+// transforms exchange through LDS only between Stockham stages.  The block
+// also emits its fp64 partial of Re<p, q> for CG.
+#include "kernels.hpp"
+#include "lengths.hpp"
+#include "reduce.hpp"
+
+namespace sense {
+
+struct EheParams {
+  const void* maps;
+  const c32* r;      // CG: residual (p = r + beta p_old); apply: unused
+  const c32* p_in;   // apply: p; CG: p_old
+  c32* p_out;        // CG: new p (same buffer as p_in)
+  c32* q;
+  const c32* tw;     // [ny]
+  const float* mu;   // [ny]
+  double* eta_part;  // [B][gridDim.x] or null
+  long nx;
+  long maps_bstride;
+  int ncoils;
+  float lambda;
+  // CG only
+  CgState* state;
+  const double* rr_part;
+  int rr_tiles;
+  double* rho_hist;
+  int hist_len;
+  double tol;
+};
+
+template <int N, int ST, bool CG>
+__global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>())
+    ehe2d_kernel(EheParams P) {
+  constexpr int T = Len<N>::T;
+  constexpr int E = Len<N>::E;
+  constexpr int TX = col_tile<T>();
+  constexpr int NT = T * TX;
+  using Rad = typename Len<N>::R;
+  constexpr int NEX = exchanges(Rad{});
+
+  __shared__ c32 xbuf[2][N * TX];
+  __shared__ c32 tw[N];
+  __shared__ float mu[N];
+  __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
+
+  const int tid = threadIdx.x;
+  const int cx = tid % TX;
+  const int t = tid / TX;
+  const int tile = blockIdx.x;
+  const int b = blockIdx.y;
+  const long x = (long)tile * TX + cx;
+  const bool valid = x < P.nx;
+  const long nx = P.nx;
+
+  double beta = 0.0;
+  if constexpr (CG) {
+    // Every block of batch element b derives the same scalars from the same
+    // partials in the same order, so no grid-wide synchronisation is needed.
+    CgState* st = P.state + b;
+    if (st->status != CG_RUNNING) return;
+    const int k = st->iter;
+    const double rho = ordered_sum(P.rr_part + (long)b * P.rr_tiles, P.rr_tiles);
+    const double rho0 = (k == 0) ? rho : st->rho0;
+    int stop = CG_RUNNING;
+    if (!finite64(rho)) stop = CG_NONFINITE;
+    else if (k > 0 && P.tol > 0.0 && sqrt(rho / rho0) < P.tol) stop = CG_CONVERGED;
+    else if (rho == 0.0) stop = CG_EXACT;
+    if (tile == 0 && tid == 0) {
+      if (k == 0) st->rho0 = rho;
+      st->rho[k & 1] = rho;
+      st->rho_cur = rho;
+      if (P.rho_hist && k < P.hist_len) P.rho_hist[(long)b * P.hist_len + k] = rho;
+      if (stop != CG_RUNNING) st->status = stop;
+    }
+    if (stop != CG_RUNNING) return;
+    if (k > 0) beta = rho / st->rho[(k - 1) & 1];
+  }
+
+  for (int i = tid; i < N; i += NT) {
+    tw[i] = P.tw[i];
+    mu[i] = P.mu[i];
+  }
+
+  const long col0 = (long)b * N * nx + x;  // element (b, row 0, x)
+  c32 p[E], q[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const long idx = col0 + (long)(t + T * j) * nx;
+    c32 v = {0.f, 0.f};
+    if (valid) {
+      v = P.p_in[idx];
+      if constexpr (CG) {
+        const c32 rv = P.r[idx];
+        v = {(float)((double)rv.re + beta * (double)v.re),
+             (float)((double)rv.im + beta * (double)v.im)};
+        P.p_out[idx] = v;
+      }
+    }
+    p[j] = v;
+    q[j] = {0.f, 0.f};
+  }
+  __syncthreads();
+
+  using SType = typename StorageT<ST>::T;
+  const SType* S = static_cast<const SType*>(P.maps) + (long)b * P.maps_bstride + x;
+  LineView<TX> v0{&xbuf[0][cx]}, v1{&xbuf[1][cx]};
+
+  for (int c = 0; c < P.ncoils; ++c) {
+    const SType* Sc = S + (long)c * N * nx;
+    c32 s[E], u[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      s[j] = valid ? load_c<ST>(Sc, (long)(t + T * j) * nx) : c32{0.f, 0.f};
+      u[j] = cmul(s[j], p[j]);
+    }
+    fft_line<N, T, -1, 0>(u, t, tw, v0, v1, Rad{});
+#pragma unroll
+    for (int j = 0; j < E; ++j) u[j] = cscale(u[j], mu[t + T * j]);
+    fft_line<N, T, +1, NEX & 1>(u, t, tw, v0, v1, Rad{});
+#pragma unroll
+    for (int j = 0; j < E; ++j) q[j] = cfma_conj(q[j], s[j], u[j]);
+  }
+
+  double eta = 0.0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    c32 qq = {q[j].re + P.lambda * p[j].re, q[j].im + P.lambda * p[j].im};
+    if (valid) {
+      P.q[col0 + (long)(t + T * j) * nx] = qq;
+      eta += (double)p[j].re * (double)qq.re + (double)p[j].im * (double)qq.im;
+    }
+  }
+  if (P.eta_part) {
+    const double tot = block_sum<NT>(eta, red);
+    if (tid == 0) P.eta_part[(long)b * gridDim.x + tile] = tot;
+  }
+}
+
+int ehe_tile_width(long ny) {
+  int tx = 0;
+  dispatch_length(ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    tx = col_tile<Len<N>::T>();
+  });
+  return tx;
+}
+
+template <bool CG>
+static hipError_t launch_ehe_impl(const Geom& g, const Tables& tb, EheParams P, hipStream_t st) {
+  hipError_t err = hipErrorInvalidValue;
+  P.tw = tb.tw_y;
+  P.mu = tb.mu_y;
+  P.nx = g.nx;
+  P.maps_bstride = g.maps_bstride;
+  P.ncoils = g.ncoils;
+  dispatch_length(g.ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    constexpr int T = Len<N>::T;
+    constexpr int TX = col_tile<T>();
+    dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)g.batch);
+    dim3 block(T * TX);
+    switch (g.maps_storage) {
+      case ST_C64: hipLaunchKernelGGL((ehe2d_kernel<N, ST_C64, CG>), grid, block, 0, st, P); break;
+      case ST_BF16: hipLaunchKernelGGL((ehe2d_kernel<N, ST_BF16, CG>), grid, block, 0, st, P); break;
+      case ST_FP16: hipLaunchKernelGGL((ehe2d_kernel<N, ST_FP16, CG>), grid, block, 0, st, P); break;
+      default: return;
+    }
+    err = hipGetLastError();
+  });
+  return err;
+}
+
+hipError_t launch_ehe(const Geom& g, const Tables& tb, const void* maps, const c32* p, c32* q,
+                      float lambda, double* eta_part, hipStream_t st) {
+  EheParams P{};
+  P.maps = maps;
+  P.p_in = p;
+  P.q = q;
+  P.lambda = lambda;
+  P.eta_part = eta_part;
+  return launch_ehe_impl<false>(g, tb, P, st);
+}
+
+hipError_t launch_ehe_cg(const Geom& g, const Tables& tb, const void* maps, const c32* r, c32* p,
+                         c32* q, float lambda, const CgArgs& cg, hipStream_t st) {
+  EheParams P{};
+  P.maps = maps;
+  P.r = r;
+  P.p_in = p;
+  P.p_out = p;
+  P.q = q;
+  P.lambda = lambda;
+  P.eta_part = cg.eta_part;
+  P.state = cg.state;
+  P.rr_part = cg.rr_part;
+  P.rr_tiles = cg.rr_tiles;
+  P.rho_hist = cg.rho_hist;
+  P.hist_len = cg.hist_len;
+  P.tol = cg.tol;
+  return launch_ehe_impl<true>(g, tb, P, st);
+}
+
+}  // namespace sense

@@ -1,0 +1,406 @@
+// Host runtime behind the C ABI (include/sense.h): plan creation (size
+// validation, fp64-built twiddle and mask tables, one workspace
+// allocation), argument checking, and the enqueue-only apply and solve calls.
+//
+// Plan creation is the once-only initialisation of the paper's process
+// model (its FFT process bakes the transform plan in init() because that
+// takes far longer than a transform); every apply call afterwards only
+// enqueues kernels on the caller's stream and never allocates.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lengths.hpp"
+#include "sense.h"
+
+namespace sense {
+
+static thread_local std::string g_last_error;
+
+static sense_status fail(sense_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+bool length_supported(long n) {
+  return dispatch_length(n, [](auto) {});
+}
+
+static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+static size_t storage_bytes(int st) { return st == ST_C64 ? 8 : 4; }
+
+struct Layout {
+  size_t tw_x, tw_y, mu_y, mask_c, rows_s, rows_u;
+  size_t work, r, p, q;
+  size_t state, eta_part, rr_part, info;
+  size_t total;
+  int eta_tiles, rr_tiles;
+};
+
+static Layout make_layout(const sense_desc& d) {
+  Layout L{};
+  const size_t nvox = (size_t)d.nx * d.ny * d.nz;
+  const size_t B = (size_t)d.batch, C = (size_t)d.ncoils;
+  const int tx = ehe_tile_width(d.ny);
+  L.eta_tiles = (int)((d.nx + tx - 1) / tx);
+  L.rr_tiles = cg_tiles((long)nvox);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  L.tw_x = take(sizeof(c32) * (size_t)d.nx);
+  L.tw_y = take(sizeof(c32) * (size_t)d.ny);
+  L.mu_y = take(sizeof(float) * (size_t)d.ny);
+  L.mask_c = take((size_t)d.ny * d.nz);
+  L.rows_s = take(sizeof(int32_t) * (size_t)d.ny * d.nz);
+  L.rows_u = take(sizeof(int32_t) * (size_t)d.ny * d.nz);
+  L.work = take(sizeof(c32) * B * C * nvox);
+  L.r = take(sizeof(c32) * B * nvox);
+  L.p = take(sizeof(c32) * B * nvox);
+  L.q = take(sizeof(c32) * B * nvox);
+  L.state = take(sizeof(CgState) * B);
+  L.eta_part = take(sizeof(double) * B * (size_t)L.eta_tiles);
+  L.rr_part = take(sizeof(double) * B * (size_t)L.rr_tiles);
+  L.info = take(sizeof(CgInfo) * B);
+  L.total = off;
+  return L;
+}
+
+static sense_status validate_desc(const sense_desc* d) {
+  if (!d) return fail(SENSE_ERR_INVALID, "desc is NULL");
+  if (d->ndim != 2 && d->ndim != 3) return fail(SENSE_ERR_INVALID, "ndim must be 2 or 3");
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->ncoils < 1 || d->batch < 1)
+    return fail(SENSE_ERR_INVALID, "sizes, coils and batch must be >= 1");
+  if (d->ndim == 2 && d->nz != 1) return fail(SENSE_ERR_INVALID, "ndim = 2 needs nz = 1");
+  for (int st : {d->maps_storage, d->kspace_storage})
+    if (st < SENSE_C64 || st > SENSE_FP16X2) return fail(SENSE_ERR_INVALID, "unknown storage format");
+  if (d->maps_shared != 0 && d->maps_shared != 1) return fail(SENSE_ERR_INVALID, "maps_shared must be 0 or 1");
+  if (d->ndim == 3) return fail(SENSE_ERR_UNSUPPORTED, "3D problems are not implemented yet");
+  if (!length_supported(d->ny))
+    return fail(SENSE_ERR_UNSUPPORTED, "ny=" + std::to_string(d->ny) + " is not a supported transform length");
+  if (d->batch > 65535 || d->ncoils > 65535) return fail(SENSE_ERR_UNSUPPORTED, "batch and coils must be <= 65535");
+  const double elems = (double)d->nx * d->ny * d->nz * d->ncoils * d->batch;
+  if (elems > 4.0e12) return fail(SENSE_ERR_UNSUPPORTED, "problem too large");
+  return SENSE_OK;
+}
+
+}  // namespace sense
+
+using namespace sense;
+
+struct sense_plan_s {
+  sense_desc d;
+  Geom g;
+  Layout L;
+  int device;
+  bool full_ops;  // nx is a supported transform length (E, E^H, CG)
+  const void* maps;
+  char* mem;
+  Tables tb;
+  int n_rows_s, n_rows_u;
+  bool profiling;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used;
+
+  template <class T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(mem + off);
+  }
+  CgArgs cg_args(double tol, double* hist, int hist_len) const {
+    CgArgs a{};
+    a.state = at<CgState>(L.state);
+    a.eta_part = at<double>(L.eta_part);
+    a.rr_part = at<double>(L.rr_part);
+    a.eta_tiles = L.eta_tiles;
+    a.rr_tiles = L.rr_tiles;
+    a.rho_hist = hist;
+    a.hist_len = hist_len;
+    a.tol = tol;
+    return a;
+  }
+};
+
+static sense_status check_plan(sense_plan p) {
+  if (!p) return fail(SENSE_ERR_INVALID, "plan is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(SENSE_ERR_STATE, "current HIP device differs from the plan's device");
+  return SENSE_OK;
+}
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + nb && y < x + na;
+}
+
+static sense_status device_fail(hipError_t e, const char* what) {
+  return fail(SENSE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static sense_status timed_ehe_begin(sense_plan p, hipStream_t st, hipEvent_t* stop) {
+  *stop = nullptr;
+  if (!p->profiling) return SENSE_OK;
+  if (p->events_used == p->events.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+      return fail(SENSE_ERR_DEVICE, "hipEventCreate failed");
+    p->events.emplace_back(a, b);
+  }
+  auto& pr = p->events[p->events_used++];
+  hipEventRecord(pr.first, st);
+  *stop = pr.second;
+  return SENSE_OK;
+}
+
+extern "C" {
+
+size_t sense_plan_device_bytes(const sense_desc* desc) {
+  if (validate_desc(desc) != SENSE_OK) return 0;
+  return make_layout(*desc).total;
+}
+
+sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const uint8_t* h_mask,
+                               void* stream, sense_plan* out) {
+  try {
+    if (!out) return fail(SENSE_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    sense_status s = validate_desc(desc);
+    if (s != SENSE_OK) return s;
+    if (!d_maps) return fail(SENSE_ERR_INVALID, "d_maps is NULL");
+    if (!h_mask) return fail(SENSE_ERR_INVALID, "h_mask is NULL");
+    const sense_desc& d = *desc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    auto* p = new (std::nothrow) sense_plan_s();
+    if (!p) return fail(SENSE_ERR_NOMEM, "host allocation failed");
+    p->d = d;
+    p->maps = d_maps;
+    p->full_ops = length_supported(d.nx);
+    p->profiling = false;
+    p->events_used = 0;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+      delete p;
+      return fail(SENSE_ERR_DEVICE, "hipGetDevice failed");
+    }
+    p->L = make_layout(d);
+    const size_t nvox = (size_t)d.nx * d.ny * d.nz;
+    p->g.nx = d.nx;
+    p->g.ny = d.ny;
+    p->g.nz = d.nz;
+    p->g.ncoils = d.ncoils;
+    p->g.batch = d.batch;
+    p->g.maps_bstride = d.maps_shared ? 0 : (long)(nvox * d.ncoils);
+    p->g.maps_storage = d.maps_storage;
+    p->g.kspace_storage = d.kspace_storage;
+
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->mem), p->L.total);
+    if (e != hipSuccess) {
+      delete p;
+      return fail(SENSE_ERR_NOMEM, "hipMalloc of " + std::to_string(p->L.total) + " bytes failed");
+    }
+
+    // Host tables: twiddles exp(-2 pi i e / n) in fp64, rounded once to fp32.
+    auto twiddles = [](long n) {
+      std::vector<c32> t((size_t)n);
+      for (long e2 = 0; e2 < n; ++e2) {
+        const double a = -2.0 * 3.141592653589793238462643383279502884 * (double)e2 / (double)n;
+        t[(size_t)e2] = c32{(float)std::cos(a), (float)std::sin(a)};
+      }
+      return t;
+    };
+    std::vector<c32> twx = twiddles(d.nx), twy = twiddles(d.ny);
+    const long rows_total = d.ny * d.nz;
+    std::vector<uint8_t> mask((size_t)rows_total);
+    std::vector<int32_t> rs, ru;
+    for (long i = 0; i < rows_total; ++i) {
+      mask[(size_t)i] = h_mask[i] ? 1 : 0;
+      (mask[(size_t)i] ? rs : ru).push_back((int32_t)i);
+    }
+    // Uncentred mask of the hybrid normal operator with the 1/ny of the
+    // unnormalised forward/inverse pair folded in.
+    std::vector<float> mu((size_t)d.ny);
+    for (long k = 0; k < d.ny; ++k)
+      mu[(size_t)k] = mask[(size_t)((k + d.ny / 2) % d.ny)] ? (float)(1.0 / (double)d.ny) : 0.f;
+    p->n_rows_s = (int)rs.size();
+    p->n_rows_u = (int)ru.size();
+
+    auto up = [&](size_t off, const void* src, size_t bytes) {
+      if (bytes == 0 || e != hipSuccess) return;
+      e = hipMemcpyAsync(p->mem + off, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    up(p->L.tw_x, twx.data(), twx.size() * sizeof(c32));
+    up(p->L.tw_y, twy.data(), twy.size() * sizeof(c32));
+    up(p->L.mu_y, mu.data(), mu.size() * sizeof(float));
+    up(p->L.mask_c, mask.data(), mask.size());
+    up(p->L.rows_s, rs.data(), rs.size() * sizeof(int32_t));
+    up(p->L.rows_u, ru.data(), ru.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      hipFree(p->mem);
+      delete p;
+      return device_fail(e, "table upload");
+    }
+    p->tb.tw_x = p->at<c32>(p->L.tw_x);
+    p->tb.tw_y = p->at<c32>(p->L.tw_y);
+    p->tb.tw_z = nullptr;
+    p->tb.mu_y = p->at<float>(p->L.mu_y);
+    p->tb.mask_c = p->at<uint8_t>(p->L.mask_c);
+    p->tb.rows_s = p->at<int32_t>(p->L.rows_s);
+    p->tb.n_rows_s = p->n_rows_s;
+    p->tb.rows_u = p->at<int32_t>(p->L.rows_u);
+    p->tb.n_rows_u = p->n_rows_u;
+    *out = p;
+    return SENSE_OK;
+  } catch (...) {
+    return fail(SENSE_ERR_INVALID, "unexpected exception in sense_plan_create");
+  }
+}
+
+sense_status sense_plan_destroy(sense_plan p) {
+  if (!p) return fail(SENSE_ERR_INVALID, "plan is NULL");
+  hipDeviceSynchronize();
+  for (auto& pr : p->events) {
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  hipFree(p->mem);
+  delete p;
+  return SENSE_OK;
+}
+
+sense_status sense_apply_E(sense_plan p, const void* d_x, void* d_y, void* stream) {
+  sense_status s = check_plan(p);
+  if (s != SENSE_OK) return s;
+  if (!d_x || !d_y) return fail(SENSE_ERR_INVALID, "d_x and d_y must be non-NULL");
+  if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
+  const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
+  const size_t xb = nvox * p->d.batch * sizeof(c32);
+  const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
+  if (overlap(d_x, xb, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_x and d_y overlap");
+  hipError_t e = launch_E(p->g, p->tb, p->maps, static_cast<const c32*>(d_x), p->at<c32>(p->L.work), d_y,
+                          static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_apply_E launch");
+}
+
+sense_status sense_apply_EH(sense_plan p, const void* d_y, void* d_x, void* stream) {
+  sense_status s = check_plan(p);
+  if (s != SENSE_OK) return s;
+  if (!d_x || !d_y) return fail(SENSE_ERR_INVALID, "d_x and d_y must be non-NULL");
+  if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
+  const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
+  const size_t xb = nvox * p->d.batch * sizeof(c32);
+  const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
+  if (overlap(d_x, xb, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_x and d_y overlap");
+  hipError_t e = launch_EH(p->g, p->tb, p->maps, d_y, p->at<c32>(p->L.work), static_cast<c32*>(d_x),
+                           static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_apply_EH launch");
+}
+
+sense_status sense_apply_EHE(sense_plan p, const void* d_p, void* d_q, double lambda, void* stream) {
+  sense_status s = check_plan(p);
+  if (s != SENSE_OK) return s;
+  if (!d_p || !d_q) return fail(SENSE_ERR_INVALID, "d_p and d_q must be non-NULL");
+  if (!std::isfinite(lambda)) return fail(SENSE_ERR_INVALID, "lambda must be finite");
+  const size_t bytes = (size_t)p->d.nx * p->d.ny * p->d.nz * p->d.batch * sizeof(c32);
+  if (overlap(d_p, bytes, d_q, bytes)) return fail(SENSE_ERR_INVALID, "d_p and d_q overlap");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t stop;
+  s = timed_ehe_begin(p, st, &stop);
+  if (s != SENSE_OK) return s;
+  hipError_t e = launch_ehe(p->g, p->tb, p->maps, static_cast<const c32*>(d_p), static_cast<c32*>(d_q),
+                            (float)lambda, p->at<double>(p->L.eta_part), st);
+  if (stop) hipEventRecord(stop, st);
+  return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_apply_EHE launch");
+}
+
+sense_status sense_cg_solve(sense_plan p, const void* d_y, void* d_x, int32_t max_iter, double rel_tol,
+                            double lambda, sense_cg_info* d_info, double* d_rho_hist, void* stream) {
+  sense_status s = check_plan(p);
+  if (s != SENSE_OK) return s;
+  if (!d_x || !d_y) return fail(SENSE_ERR_INVALID, "d_x and d_y must be non-NULL");
+  if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
+  if (max_iter < 0) return fail(SENSE_ERR_INVALID, "max_iter must be >= 0");
+  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return fail(SENSE_ERR_INVALID, "rel_tol must be finite and >= 0");
+  if (!std::isfinite(lambda)) return fail(SENSE_ERR_INVALID, "lambda must be finite");
+  const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
+  const size_t xb = nvox * p->d.batch * sizeof(c32);
+  const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
+  if (overlap(d_x, xb, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_x and d_y overlap");
+  if (overlap(d_x, xb, p->mem, p->L.total) || overlap(d_y, yb, p->mem, p->L.total))
+    return fail(SENSE_ERR_INVALID, "buffers overlap the plan workspace");
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  c32* x = static_cast<c32*>(d_x);
+  c32* r = p->at<c32>(p->L.r);
+  c32* pv = p->at<c32>(p->L.p);
+  c32* q = p->at<c32>(p->L.q);
+  const CgArgs cg = p->cg_args(rel_tol, d_rho_hist, d_rho_hist ? max_iter + 1 : 0);
+
+  hipError_t e = launch_EH(p->g, p->tb, p->maps, d_y, p->at<c32>(p->L.work), r, st);
+  if (e == hipSuccess) e = launch_cg_init(p->g, r, x, r, pv, cg, st);
+  for (int k = 0; k < max_iter && e == hipSuccess; ++k) {
+    hipEvent_t stop;
+    s = timed_ehe_begin(p, st, &stop);
+    if (s != SENSE_OK) return s;
+    e = launch_ehe_cg(p->g, p->tb, p->maps, r, pv, q, (float)lambda, cg, st);
+    if (stop) hipEventRecord(stop, st);
+    if (e == hipSuccess) e = launch_cg_update(p->g, x, r, pv, q, cg, st);
+  }
+  CgInfo* info = p->at<CgInfo>(p->L.info);
+  if (e == hipSuccess) e = launch_cg_finish(p->g, cg, info, st);
+  if (e == hipSuccess && d_info)
+    e = hipMemcpyAsync(d_info, info, sizeof(CgInfo) * p->d.batch, hipMemcpyDeviceToDevice, st);
+  return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_cg_solve launch");
+}
+
+sense_status sense_plan_cg_info(sense_plan p, sense_cg_info* h_info, void* stream) {
+  sense_status s = check_plan(p);
+  if (s != SENSE_OK) return s;
+  if (!h_info) return fail(SENSE_ERR_INVALID, "h_info is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(h_info, p->at<CgInfo>(p->L.info), sizeof(CgInfo) * p->d.batch,
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_plan_cg_info copy");
+}
+
+sense_status sense_plan_set_profiling(sense_plan p, int32_t enable) {
+  if (!p) return fail(SENSE_ERR_INVALID, "plan is NULL");
+  p->profiling = enable != 0;
+  p->events_used = 0;
+  return SENSE_OK;
+}
+
+sense_status sense_plan_profile(sense_plan p, int64_t* n_launches, double* total_ms) {
+  if (!p) return fail(SENSE_ERR_INVALID, "plan is NULL");
+  if (!n_launches || !total_ms) return fail(SENSE_ERR_INVALID, "outputs must be non-NULL");
+  double tot = 0.0;
+  for (size_t i = 0; i < p->events_used; ++i) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(p->events[i].second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p->events[i].first, p->events[i].second);
+    if (e != hipSuccess) return device_fail(e, "hipEventElapsedTime");
+    tot += ms;
+  }
+  *n_launches = (int64_t)p->events_used;
+  *total_ms = tot;
+  p->events_used = 0;
+  return SENSE_OK;
+}
+
+const char* sense_last_error(void) { return g_last_error.c_str(); }
+
+const char* sense_version(void) { return "sense-gfx950 0.1"; }
+
+}  // extern "C"
+
+static_assert(sizeof(sense_cg_info) == sizeof(CgInfo), "info layout");

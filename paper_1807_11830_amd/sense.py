@@ -1,0 +1,293 @@
+"""ctypes binding of the gfx950 CG-SENSE library (include/sense.h).
+
+Argument marshalling only: torch supplies device memory and the current
+stream, every operator step runs in the HIP kernels of libsense_gfx950.so.
+There is no fallback: if the library is missing or a call fails, a
+:class:`SenseError` is raised.
+
+Names follow the operator notation of the paper (arXiv 1807.11830, Eq. (1)
+and the multicoil model around it): sensitivity maps S, k-space y, image x,
+sampling mask M, and the operators E, E^H (``EH``) and E^H E (``EHE``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsense_gfx950.so")
+
+C64, BF16X2, FP16X2 = 0, 1, 2
+STORAGE = {"c64": C64, "bf16": BF16X2, "fp16": FP16X2}
+MAXITER, CONVERGED, EXACT, BREAKDOWN, NONFINITE = 0, 1, 2, 3, 4
+STATUS_NAMES = {MAXITER: "maxiter", CONVERGED: "converged", EXACT: "exact",
+                BREAKDOWN: "breakdown", NONFINITE: "nonfinite"}
+ERRORS = {1: "invalid argument", 2: "unsupported", 3: "out of memory", 4: "device error",
+          5: "bad state"}
+
+# Lengths with compiled transforms (Ny always; Nx for E, E^H and CG).
+SUPPORTED_LENGTHS = (8, 16, 32, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384)
+
+
+class SenseError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sense error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
+                ("nz", ctypes.c_int64), ("ncoils", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("maps_storage", ctypes.c_int32), ("kspace_storage", ctypes.c_int32),
+                ("maps_shared", ctypes.c_int32)]
+
+
+class CgInfo(ctypes.Structure):
+    _fields_ = [("iters_run", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rho0", ctypes.c_double), ("rho_final", ctypes.c_double)]
+
+
+ABI_FUNCTIONS = ("sense_plan_device_bytes", "sense_plan_create", "sense_plan_destroy",
+                 "sense_apply_E", "sense_apply_EH", "sense_apply_EHE", "sense_cg_solve",
+                 "sense_plan_cg_info", "sense_plan_set_profiling", "sense_plan_profile",
+                 "sense_last_error", "sense_version")
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SenseError(4, f"{LIB_PATH} is missing: build it with "
+                            "`python -m paper_1807_11830_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.sense_plan_device_bytes.argtypes = [ctypes.POINTER(Desc)]
+    L.sense_plan_device_bytes.restype = ctypes.c_size_t
+    L.sense_plan_create.argtypes = [ctypes.POINTER(Desc), P, P, P, ctypes.POINTER(P)]
+    L.sense_plan_destroy.argtypes = [P]
+    L.sense_apply_E.argtypes = [P, P, P, P]
+    L.sense_apply_EH.argtypes = [P, P, P, P]
+    L.sense_apply_EHE.argtypes = [P, P, P, D, P]
+    L.sense_cg_solve.argtypes = [P, P, P, I32, D, D, P, P, P]
+    L.sense_plan_cg_info.argtypes = [P, P, P]
+    L.sense_plan_set_profiling.argtypes = [P, I32]
+    L.sense_plan_profile.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(D)]
+    L.sense_last_error.argtypes = []
+    L.sense_last_error.restype = ctypes.c_char_p
+    L.sense_version.argtypes = []
+    L.sense_version.restype = ctypes.c_char_p
+    for f in ABI_FUNCTIONS:
+        if f not in ("sense_plan_device_bytes", "sense_last_error", "sense_version"):
+            getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise SenseError(rc, lib().sense_last_error().decode())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def to_storage(a: torch.Tensor, storage: str) -> torch.Tensor:
+    """Complex tensor -> the library's interleaved storage (input marshalling).
+
+    c64 returns a contiguous complex64 tensor; bf16/fp16 return the
+    interleaved (re, im) 16-bit pairs with round-to-nearest-even."""
+    a = a.to(torch.complex64).contiguous()
+    if storage == "c64":
+        return a
+    dt = torch.bfloat16 if storage == "bf16" else torch.float16
+    return torch.view_as_real(a).to(dt).contiguous()
+
+
+def from_storage(a: torch.Tensor, storage: str) -> torch.Tensor:
+    if storage == "c64":
+        return a
+    return torch.view_as_complex(a.to(torch.float32).contiguous())
+
+
+def device_bytes(nx, ny, ncoils, batch, nz=1, ndim=2, maps_storage="c64", kspace_storage="c64",
+                 maps_shared=True) -> int:
+    d = Desc(ndim, nx, ny, nz, ncoils, batch, STORAGE[maps_storage], STORAGE[kspace_storage],
+             int(maps_shared))
+    return int(lib().sense_plan_device_bytes(ctypes.byref(d)))
+
+
+@dataclass
+class CgResult:
+    x: torch.Tensor
+    iters: np.ndarray
+    status: np.ndarray
+    rho0: np.ndarray
+    rho_final: np.ndarray
+    rho_hist: torch.Tensor | None
+
+
+class Plan:
+    """A SENSE operator instance: maps, mask and sizes fixed at creation.
+
+    maps: complex tensor on the GPU, [C][Ny][Nx] (shared by every batch
+          element) or [B][C][Ny][Nx]; converted to ``maps_storage`` once.
+    mask: uint8 array of Ny entries in centred order (DC at Ny // 2).
+    """
+
+    def __init__(self, maps: torch.Tensor, mask, batch: int = 1, maps_storage: str = "c64",
+                 kspace_storage: str = "c64", stream=None):
+        if not maps.is_cuda:
+            raise SenseError(1, "maps must be a GPU tensor")
+        if maps.dim() == 3:
+            shared = True
+            ncoils, ny, nx = maps.shape
+        elif maps.dim() == 4:
+            shared = False
+            if maps.shape[0] != batch:
+                raise SenseError(1, "maps batch dimension must equal batch")
+            _, ncoils, ny, nx = maps.shape
+        else:
+            raise SenseError(1, "maps must be [C][Ny][Nx] or [B][C][Ny][Nx]")
+        self.nx, self.ny, self.ncoils, self.batch = int(nx), int(ny), int(ncoils), int(batch)
+        self.maps_storage, self.kspace_storage = maps_storage, kspace_storage
+        self.maps_shared = shared
+        self.device = maps.device
+        if maps.dtype in (torch.bfloat16, torch.float16):
+            self._maps = maps.contiguous()
+        else:
+            self._maps = to_storage(maps, maps_storage)
+        m = np.ascontiguousarray(np.asarray(mask if not torch.is_tensor(mask) else mask.cpu().numpy()),
+                                 dtype=np.uint8)
+        if m.size != self.ny:
+            raise SenseError(1, f"mask needs {self.ny} entries")
+        self.mask = m
+        self.desc = Desc(2, self.nx, self.ny, 1, self.ncoils, self.batch, STORAGE[maps_storage],
+                         STORAGE[kspace_storage], int(shared))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().sense_plan_create(ctypes.byref(self.desc), _ptr(self._maps),
+                                           m.ctypes.data_as(ctypes.c_void_p), _stream(stream),
+                                           ctypes.byref(h)))
+        self._h = h
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            with torch.cuda.device(self.device):
+                _check(lib().sense_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- shapes ------------------------------------------------------------
+    @property
+    def image_shape(self):
+        return (self.batch, self.ny, self.nx)
+
+    @property
+    def kspace_shape(self):
+        return (self.batch, self.ncoils, self.ny, self.nx)
+
+    def _img(self, t: torch.Tensor, name: str):
+        if t.dtype != torch.complex64 or not t.is_contiguous() or t.device != self.device:
+            raise SenseError(1, f"{name} must be a contiguous complex64 tensor on {self.device}")
+        if t.numel() != self.batch * self.ny * self.nx:
+            raise SenseError(1, f"{name} must have {self.image_shape} elements")
+        return t
+
+    def _ksp(self, t: torch.Tensor, name: str):
+        if self.kspace_storage == "c64":
+            ok = t.dtype == torch.complex64 and t.numel() == self.batch * self.ncoils * self.ny * self.nx
+        else:
+            dt = torch.bfloat16 if self.kspace_storage == "bf16" else torch.float16
+            ok = t.dtype == dt and t.numel() == 2 * self.batch * self.ncoils * self.ny * self.nx
+        if not ok or not t.is_contiguous() or t.device != self.device:
+            raise SenseError(1, f"{name} must be contiguous k-space in {self.kspace_storage} storage")
+        return t
+
+    def new_kspace(self):
+        if self.kspace_storage == "c64":
+            return torch.empty(self.kspace_shape, dtype=torch.complex64, device=self.device)
+        dt = torch.bfloat16 if self.kspace_storage == "bf16" else torch.float16
+        return torch.empty(self.kspace_shape + (2,), dtype=dt, device=self.device)
+
+    # -- operators -----------------------------------------------------------
+    def E(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        x = self._img(x, "x")
+        y = self.new_kspace() if out is None else self._ksp(out, "out")
+        with torch.cuda.device(self.device):
+            _check(lib().sense_apply_E(self._h, _ptr(x), _ptr(y), _stream(stream)))
+        return y
+
+    def EH(self, y: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        y = self._ksp(y, "y")
+        x = torch.empty(self.image_shape, dtype=torch.complex64, device=self.device) if out is None \
+            else self._img(out, "out")
+        with torch.cuda.device(self.device):
+            _check(lib().sense_apply_EH(self._h, _ptr(y), _ptr(x), _stream(stream)))
+        return x
+
+    def EHE(self, p: torch.Tensor, lam: float = 0.0, out: torch.Tensor | None = None,
+            stream=None) -> torch.Tensor:
+        p = self._img(p, "p")
+        q = torch.empty_like(p) if out is None else self._img(out, "out")
+        with torch.cuda.device(self.device):
+            _check(lib().sense_apply_EHE(self._h, _ptr(p), _ptr(q), float(lam), _stream(stream)))
+        return q
+
+    def cg(self, y: torch.Tensor, max_iter: int, tol: float = 0.0, lam: float = 0.0,
+           out: torch.Tensor | None = None, history: bool = False, stream=None,
+           sync: bool = True) -> CgResult:
+        """CG-SENSE.  With sync=False the info arrays are left unread (None)."""
+        y = self._ksp(y, "y")
+        x = torch.empty(self.image_shape, dtype=torch.complex64, device=self.device) if out is None \
+            else self._img(out, "out")
+        hist = torch.zeros((self.batch, max_iter + 1), dtype=torch.float64, device=self.device) \
+            if history else None
+        with torch.cuda.device(self.device):
+            _check(lib().sense_cg_solve(self._h, _ptr(y), _ptr(x), int(max_iter), float(tol),
+                                        float(lam), None,
+                                        _ptr(hist) if hist is not None else None, _stream(stream)))
+            if not sync:
+                return CgResult(x, None, None, None, None, hist)
+            info = (CgInfo * self.batch)()
+            _check(lib().sense_plan_cg_info(self._h, ctypes.cast(info, ctypes.c_void_p),
+                                            _stream(stream)))
+        return CgResult(x, np.array([i.iters_run for i in info]), np.array([i.status for i in info]),
+                        np.array([i.rho0 for i in info]), np.array([i.rho_final for i in info]), hist)
+
+    # -- profiling -------------------------------------------------------------
+    def set_profiling(self, on: bool):
+        _check(lib().sense_plan_set_profiling(self._h, int(bool(on))))
+
+    def profile(self):
+        """(number of timed E^H E launches, total ms); clears the record."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        with torch.cuda.device(self.device):
+            _check(lib().sense_plan_profile(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return int(n.value), float(ms.value)

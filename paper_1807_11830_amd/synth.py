@@ -103,18 +103,19 @@ def _bump(u, v, w, centre, theta, width=0.6):
     return mag * np.exp(1j * phase)
 
 
-def coil_maps2d(n: int, ncoils: int, ny: int | None = None) -> np.ndarray:
+def coil_maps2d(n: int, ncoils: int, ny: int | None = None, rotation: float = 0.0) -> np.ndarray:
     """Gaussian-bump coil sensitivities [C][Ny][Nx] with sum_c |S_c|^2 = 1.
 
-    Coil c sits at angle 2*pi*c/C on the unit circle; magnitude
-    exp(-|r - r_c|^2 / (2 * 0.6^2)); phase (pi/2)(u cos t + v sin t) + t.
+    Coil c sits at angle t = 2*pi*c/C + rotation on the unit circle;
+    magnitude exp(-|r - r_c|^2 / (2 * 0.6^2)); phase (pi/2)(u cos t + v sin t) + t.
+    A per-slice rotation gives every slice of a batch its own maps.
     """
     ny = n if ny is None else ny
     u = _grid(n)[None, :]
     v = _grid(ny)[:, None]
     maps = np.empty((ncoils, ny, n), dtype=np.complex128)
     for c in range(ncoils):
-        t = 2.0 * np.pi * c / ncoils
+        t = 2.0 * np.pi * c / ncoils + rotation
         maps[c] = _bump(u, v, 0.0, (np.cos(t), np.sin(t), 0.0), t)
     maps /= np.sqrt(np.sum(np.abs(maps) ** 2, axis=0, keepdims=True))
     return maps
@@ -249,14 +250,21 @@ SLICE_256 = Workload2D("cgsense_256x256_c12_vdr4_k30", 256, 12, 1, 30, "vd", 4.0
 PREC_384 = Workload2D("cgsense_384x384_c32_b8_vdr4_k40", 384, 32, 8, 40, "vd", 4.0, 24)
 
 
-def slice_inputs(w: Workload2D, batch: int | None = None, seed: int = SEED_PHANTOM):
-    """Image batch [B][N][N], maps [C][N][N] and mask [N] for a 2D workload.
+def slice_inputs(w: Workload2D, batch: int | None = None, seed: int = SEED_PHANTOM,
+                 per_slice_maps: bool = False):
+    """Image batch [B][N][N], maps and mask [N] for a 2D workload.
 
-    Batch element b uses phantom seed `seed + b`, so slices differ.
+    Batch element b uses phantom seed `seed + b`, so slices differ.  Maps are
+    [C][N][N] (shared), or [B][C][N][N] with per_slice_maps, slice b rotated
+    by 2*pi*b / (B*C).
     """
     b = w.batch if batch is None else batch
     imgs = np.stack([phantom2d(w.n, seed=seed + i) for i in range(b)])
-    maps = coil_maps2d(w.n, w.ncoils)
+    if per_slice_maps:
+        maps = np.stack([coil_maps2d(w.n, w.ncoils, rotation=2.0 * np.pi * i / (b * w.ncoils))
+                         for i in range(b)])
+    else:
+        maps = coil_maps2d(w.n, w.ncoils)
     return imgs, maps, w.mask_array()
 
 

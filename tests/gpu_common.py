@@ -1,0 +1,66 @@
+"""Shared helpers of the GPU parity tests: seeded inputs, rounding to the
+GPU's complex64 inputs, and relative-L2 error per batch element.
+
+The oracle always receives the complex64-rounded inputs the GPU receives
+(widened back to complex128), so a comparison measures the GPU arithmetic,
+not input rounding.
+"""
+import sys
+
+import numpy as np
+import torch
+
+from paper_1807_11830_amd import synth
+
+DEV = "cuda:0"
+
+# Tolerance of a single fp32 operator apply (E, E^H, E^H E) against the FP64
+# oracle, relative L2 per batch element.
+TOL_FP32 = 1e-5
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def c64(a: np.ndarray) -> np.ndarray:
+    """Round to complex64 and widen back: the values the GPU sees."""
+    return np.asarray(a).astype(np.complex64).astype(np.complex128)
+
+
+def to_dev(a: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(np.complex64))).to(DEV)
+
+
+def to_host(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def rel_l2(got: np.ndarray, ref: np.ndarray, batch_axis: bool = True) -> float:
+    """max over batch elements of ||got - ref|| / ||ref||."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    if not batch_axis:
+        return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    errs = [np.linalg.norm((got[b] - ref[b]).ravel()) / np.linalg.norm(ref[b].ravel())
+            for b in range(ref.shape[0])]
+    return float(max(errs))
+
+
+def rand_case(ny, nx, nc, batch, per_batch_maps, seed=0, accel=2.0):
+    """Random complex maps/images and a VD mask: rounded to complex64."""
+    maps_shape = (batch, nc, ny, nx) if per_batch_maps else (nc, ny, nx)
+    maps = c64(0.5 * synth.complex_normal(maps_shape, seed + 1))
+    x = c64(synth.complex_normal((batch, ny, nx), seed + 2))
+    mask = synth.mask_variable_density(ny, accel, max(2, ny // 8), seed=seed + 3)
+    return maps, x, mask
+
+
+def quantise(a: np.ndarray, storage: str) -> np.ndarray:
+    """complex64 -> 16-bit pair storage -> back to complex128 (RNE via torch)."""
+    if storage == "c64":
+        return c64(a)
+    dt = torch.bfloat16 if storage == "bf16" else torch.float16
+    t = torch.view_as_real(torch.from_numpy(np.asarray(a).astype(np.complex64))).to(dt)
+    return torch.view_as_complex(t.to(torch.float32).contiguous()).numpy().astype(np.complex128)

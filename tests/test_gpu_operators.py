@@ -1,0 +1,170 @@
+"""GPU parity of the operators E, E^H and the fused E^H E against the FP64
+oracle, through the C ABI (ctypes binding).  Needs an MI355X.
+
+Bar: relative L2 error <= 1e-5 per batch element for fp32 storage (the
+tolerance of the stated fp32 path); shapes span several column tiles and a
+ragged last tile, every compiled transform length, shared and per-batch
+maps, and lambda != 0.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import TOL_FP32, c64, log, quantise, rand_case, rel_l2, to_dev, to_host
+from paper_1807_11830_amd import sense, synth
+
+pytestmark = pytest.mark.gpu
+
+EHE_CASES = [  # ny, nx, ncoils, batch, per_batch_maps
+    (64, 64, 4, 1, False),     # 64x64, 4 coils
+    (256, 256, 12, 1, False),  # 256x256, 12 coils
+    (64, 72, 3, 2, True),      # ragged last tile, per-batch maps
+    (256, 40, 5, 3, False),
+] + [(n, 40, 2, 1, False) for n in sense.SUPPORTED_LENGTHS]
+
+
+@pytest.mark.parametrize("ny,nx,nc,b,per", EHE_CASES)
+def test_ehe_matches_oracle(ny, nx, nc, b, per):
+    log(f"EHE ny={ny} nx={nx} C={nc} B={b} per_batch_maps={per}")
+    maps, x, mask = rand_case(ny, nx, nc, b, per, seed=ny + nx)
+    ref = oracle.A(x, maps, mask)
+    with sense.Plan(to_dev(maps), mask, batch=b) as plan:
+        q = plan.EHE(to_dev(x))
+        torch.cuda.synchronize()
+    err = rel_l2(to_host(q), ref)
+    log(f"  rel-L2 {err:.3e}")
+    assert err <= TOL_FP32
+
+
+def test_ehe_lambda():
+    maps, x, mask = rand_case(128, 48, 3, 2, False, seed=5)
+    ref = oracle.A(x, maps, mask, lam=0.37)
+    with sense.Plan(to_dev(maps), mask, batch=2) as plan:
+        q = plan.EHE(to_dev(x), lam=0.37)
+        torch.cuda.synchronize()
+    assert rel_l2(to_host(q), ref) <= TOL_FP32
+
+
+E_CASES = [  # ny, nx, ncoils, batch, per_batch_maps
+    (64, 64, 4, 1, False),
+    (256, 256, 12, 1, False),
+    (48, 80, 3, 2, True),
+    (384, 160, 2, 1, False),
+    (192, 320, 2, 1, False),
+    (96, 128, 2, 2, False),
+    (8, 16, 2, 1, False),
+    (32, 8, 3, 1, False),
+]
+
+
+@pytest.mark.parametrize("ny,nx,nc,b,per", E_CASES)
+def test_E_and_EH_match_oracle(ny, nx, nc, b, per):
+    log(f"E/EH ny={ny} nx={nx} C={nc} B={b}")
+    maps, x, mask = rand_case(ny, nx, nc, b, per, seed=3 * ny + nx)
+    y_ref = oracle.E(x, maps, mask)
+    yin = c64(synth.complex_normal((b, nc, ny, nx), 77))
+    x_ref = oracle.EH(yin, maps, mask)
+    with sense.Plan(to_dev(maps), mask, batch=b) as plan:
+        y = plan.E(to_dev(x))
+        xh = plan.EH(to_dev(yin))
+        torch.cuda.synchronize()
+    y = to_host(y)
+    assert np.all(y[:, :, mask == 0, :] == 0)
+    e1 = rel_l2(y, y_ref)
+    e2 = rel_l2(to_host(xh), x_ref)
+    log(f"  E {e1:.3e}  EH {e2:.3e}")
+    assert e1 <= TOL_FP32 and e2 <= TOL_FP32
+
+
+def test_adjoint_identity_on_gpu():
+    maps, x, mask = rand_case(128, 96, 4, 2, True, seed=9)
+    yin = c64(synth.complex_normal((2, 4, 128, 96), 10))
+    with sense.Plan(to_dev(maps), mask, batch=2) as plan:
+        ex = to_host(plan.E(to_dev(x)))
+        ehy = to_host(plan.EH(to_dev(yin)))
+    lhs = np.vdot(ex.ravel(), (yin * mask[None, None, :, None]).ravel())
+    rhs = np.vdot(x.ravel(), ehy.ravel())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_fused_equals_composed():
+    """The fused hybrid-space E^H E equals E^H(E p) on the GPU."""
+    maps, x, mask = rand_case(192, 64, 4, 2, False, seed=12)
+    with sense.Plan(to_dev(maps), mask, batch=2) as plan:
+        xd = to_dev(x)
+        q1 = to_host(plan.EHE(xd))
+        q2 = to_host(plan.EH(plan.E(xd)))
+    assert rel_l2(q1, q2) <= 2 * TOL_FP32
+
+
+def test_eq1_fully_sampled_on_gpu():
+    """Full mask: E^H y is the paper's Eq. (1) up to the unitary scale."""
+    ny = nx = 160  # the paper's 160x160 cine frames, 8 coils
+    nc, b = 8, 2
+    maps = c64(synth.coil_maps2d(nx, nc))
+    y = c64(synth.complex_normal((b, nc, ny, nx), 4))
+    full = np.ones(ny, np.uint8)
+    ref = oracle.EH(y, maps, full) * oracle.eq1_factor(ny * nx)
+    with sense.Plan(to_dev(maps), full, batch=b) as plan:
+        got = to_host(plan.EH(to_dev(y))) * oracle.eq1_factor(ny * nx)
+    assert rel_l2(got, ref) <= TOL_FP32
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_reduced_precision_maps(storage):
+    """16-bit maps: GPU arithmetic vs the oracle on the quantised maps at the
+    fp32 bar; total error vs the unquantised oracle under 1e-2."""
+    ny = nx = 128
+    nc, b = 8, 2
+    maps = c64(synth.coil_maps2d(nx, nc))
+    x = c64(np.stack([synth.phantom2d(nx, seed=s) for s in range(b)]))
+    mask = synth.mask_variable_density(ny, 4.0, 16)
+    mq = quantise(maps, storage)
+    with sense.Plan(to_dev(maps), mask, batch=b, maps_storage=storage) as plan:
+        q = to_host(plan.EHE(to_dev(x)))
+    e_arith = rel_l2(q, oracle.A(x, mq, mask))
+    e_total = rel_l2(q, oracle.A(x, maps, mask))
+    log(f"{storage}: arithmetic {e_arith:.3e} total {e_total:.3e}")
+    assert e_arith <= TOL_FP32
+    assert e_total <= 1e-2
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_reduced_precision_kspace(storage):
+    ny = nx = 64
+    nc, b = 4, 1
+    maps = c64(synth.coil_maps2d(nx, nc))
+    x = c64(synth.phantom2d(nx)[None])
+    mask = synth.mask_regular(ny, 2, 8)
+    yref = oracle.E(x, maps, mask)
+    with sense.Plan(to_dev(maps), mask, batch=b, kspace_storage=storage) as plan:
+        y = plan.E(to_dev(x))
+        ycpx = sense.from_storage(y, storage)
+        xb = to_host(plan.EH(y))
+    # one rounding of each output component to 8 (bf16) or 11 (fp16) bits
+    bound = 2.0 ** -8 if storage == "bf16" else 2.0 ** -11
+    assert rel_l2(to_host(ycpx), yref) <= bound
+    assert rel_l2(xb, oracle.EH(quantise(yref, storage), maps, mask)) <= 3 * TOL_FP32
+
+
+def test_invalid_calls_on_gpu():
+    maps, x, mask = rand_case(64, 64, 2, 1, False)
+    with sense.Plan(to_dev(maps), mask, batch=1) as plan:
+        p = to_dev(x)
+        with pytest.raises(sense.SenseError, match="overlap"):
+            sense._check(sense.lib().sense_apply_EHE(plan._h, sense._ptr(p), sense._ptr(p), 0.0, None))
+        with pytest.raises(sense.SenseError):
+            plan.EHE(p.to(torch.complex128))
+    with pytest.raises(sense.SenseError, match="unsupported|ny=100"):
+        sense.Plan(to_dev(0.5 * synth.complex_normal((2, 100, 64), 1)), np.ones(100, np.uint8))
+
+
+def test_deterministic():
+    maps, x, mask = rand_case(256, 64, 6, 2, False, seed=2)
+    with sense.Plan(to_dev(maps), mask, batch=2) as plan:
+        xd = to_dev(x)
+        a = plan.EHE(xd).clone()
+        b = plan.EHE(xd)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
