@@ -34,14 +34,16 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=160)
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--maps-storage", default="c64", choices=["c64", "bf16", "fp16"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also time a 1 GiB device-to-device copy (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -77,14 +79,17 @@ def cpu_baseline(w, maps0, mask, y0, target_s):
     t0 = time.perf_counter()
     oracle.A(oracle.EH(y0, maps0, mask), maps0, mask)
     t_a = time.perf_counter() - t0
-    k = int(max(1, min(w.iters, round(target_s / max(t_a, 1e-3)))))
+    # whole solves of the workload's iteration count, repeated to ~target_s
+    k = w.iters
+    reps = int(max(1, round(target_s / max(t_a * (k + 1), 1e-3))))
     t0 = time.perf_counter()
-    oracle.cg(y0, maps0, mask, k)
+    for _ in range(reps):
+        oracle.cg(y0, maps0, mask, k)
     dt = time.perf_counter() - t0
-    return dict(value=k / dt, unit="applies/s", cores=min(threads, w.ncoils), kind="oracle",
-                sample=f"1 slice {w.n}x{w.n}, {w.ncoils} coils: E^H y + {k} CG iterations "
-                       f"(E^H E composed as E^H(E p), fp64, {min(threads, w.ncoils)} OpenMP threads "
-                       f"over coils) in {dt:.1f} s")
+    return dict(value=reps * k / dt, unit="applies/s", cores=min(threads, w.ncoils), kind="oracle",
+                sample=f"1 slice {w.n}x{w.n}, {w.ncoils} coils, {reps} x (E^H y + {k} CG iterations), "
+                       f"E^H E composed as E^H(E p) in fp64, {min(threads, w.ncoils)} OpenMP threads "
+                       f"over coils, {dt:.1f} s")
 
 
 def main():
@@ -180,6 +185,20 @@ def main():
                       "achieved_gbs": apply_bytes / apply_s / 1e9,
                       "applies_per_s": B / apply_s},
     }
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.complex64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        ev1.record()
+        torch.cuda.synchronize()
+        cms = ev0.elapsed_time(ev1) / 5
+        out["copy_1gib"] = {"ms": cms, "gbs_read_plus_write": 2 * (1 << 30) / cms / 1e6}
+        log(f"bench: 1 GiB copy {cms:.3f} ms ({2 * (1 << 30) / cms / 1e6:.0f} GB/s read+write)")
+        del src, dst
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         y0 = y[0].cpu().numpy()

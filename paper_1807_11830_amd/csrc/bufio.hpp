@@ -1,0 +1,53 @@
+// Raw buffer loads and stores for the column kernels.  A buffer resource
+// (base, size) lives in scalar registers; each access takes a per-thread
+// byte offset (one VGPR) plus a wavefront-uniform byte offset (SGPR), so the
+// strided row accesses of a column need no 64-bit per-access address math.
+// Every offset used here stays inside the resource's range.
+#pragma once
+
+#include "cplx.hpp"
+
+namespace sense {
+
+// Word 3 of a raw gfx9 buffer descriptor (32-bit data format, no swizzle).
+constexpr int kBufWord3 = 0x00020000;
+
+struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ __forceinline__ Buf make_buf(const void* base, uint32_t bytes) {
+  return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3)};
+}
+
+__device__ __forceinline__ c32 buf_load_c64(Buf b, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(c32, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
+}
+
+__device__ __forceinline__ uint32_t buf_load_b32(Buf b, uint32_t voff, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)soff, 0);
+}
+
+__device__ __forceinline__ void buf_store_c64(Buf b, c32 v, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned int, v),
+                                        b.r, (int)voff, (int)soff, 0);
+}
+
+// Complex value in storage ST at (voff + soff) element offsets, converted to fp32.
+template <int ST>
+__device__ __forceinline__ c32 buf_load_st(Buf b, uint32_t vi, uint32_t si) {
+  if constexpr (ST == ST_C64) {
+    return buf_load_c64(b, vi * 8u, si * 8u);
+  } else {
+    const uint32_t w = buf_load_b32(b, vi * 4u, si * 4u);
+    if constexpr (ST == ST_BF16) {
+      return {bf16_to_f32(w & 0xffffu), bf16_to_f32(w >> 16)};
+    } else {
+      _Float16 lo = __builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+      _Float16 hi = __builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+      return {(float)lo, (float)hi};
+    }
+  }
+}
+
+}  // namespace sense

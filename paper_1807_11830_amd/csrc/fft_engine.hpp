@@ -21,6 +21,8 @@
 
 #include "dft_small.hpp"
 
+#include <type_traits>
+
 namespace sense {
 
 template <int... Rs>
@@ -40,10 +42,44 @@ struct LineView {
   __device__ __forceinline__ c32& at(int p) const { return base[p * PS]; }
 };
 
-// One Stockham stage.  tw[e] = exp(-2 pi i e / N), e < N (fp32 from fp64).
-template <int N, int T, int R, int NS, int DIR, bool LAST, class View>
-__device__ __forceinline__ void stockham_stage(c32* v, int t, const c32* __restrict__ tw,
-                                               View out) {
+// Twiddle sources.  A stage of span NS and radix R multiplies input r of
+// butterfly jb (m-th of the thread) by exp(DIR 2 pi i r (jb mod NS) / (NS R)),
+// read from tw[e] = exp(-2 pi i e / N) at e = (jb mod NS) * r * N / (NS R).
+struct TwTable {
+  const c32* tw;  // N entries (LDS or global)
+  template <int N, int NS, int R, int m, int r>
+  __device__ __forceinline__ c32 get(int jm) const {
+    return tw[jm * (r * (N / (NS * R)))];
+  }
+};
+
+// Register copy of the second-stage twiddles of a two-stage transform, loaded
+// once per block and reused by every forward and inverse transform.
+template <int N, int T, int R1, int R2>
+struct TwRegs2 {
+  static constexpr int E = N / T;
+  static constexpr int M = E / R2;
+  c32 w[M * (R2 - 1)];
+  __device__ __forceinline__ void load(const c32* tw, int t) {
+    sfor<M>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      const int jm = (t + T * m) % R1;
+      sfor<R2 - 1>([&](auto rc) {
+        constexpr int r = decltype(rc)::value + 1;
+        w[m * (R2 - 1) + r - 1] = tw[jm * (r * (N / (R1 * R2)))];
+      });
+    });
+  }
+  template <int N_, int NS, int R, int m, int r>
+  __device__ __forceinline__ c32 get(int) const {
+    static_assert(NS == R1 && R == R2, "register twiddles cover the second stage only");
+    return w[m * (R2 - 1) + r - 1];
+  }
+};
+
+// One Stockham stage.
+template <int N, int T, int R, int NS, int DIR, bool LAST, class View, class Tw>
+__device__ __forceinline__ void stockham_stage(c32* v, int t, const Tw& tw, View out) {
   constexpr int E = N / T;
   constexpr int M = E / R;
   static_assert(E % R == 0, "each radix must divide the elements per thread");
@@ -54,10 +90,9 @@ __device__ __forceinline__ void stockham_stage(c32* v, int t, const c32* __restr
     const int jb = t + T * m;
     const int jm = jb % NS;
     if constexpr (NS > 1) {
-      constexpr int step = N / (NS * R);
       sfor<R - 1>([&](auto rc) {
         constexpr int r = decltype(rc)::value + 1;
-        const c32 w = tw[jm * (r * step)];
+        const c32 w = tw.template get<N, NS, R, m, r>(jm);
         a[r] = (DIR < 0) ? cmul(a[r], w) : cmulc(a[r], w);
       });
     }
@@ -73,25 +108,60 @@ __device__ __forceinline__ void stockham_stage(c32* v, int t, const c32* __restr
 
 // Recursive driver over the radix list.  BUF selects the LDS buffer of the
 // next exchange.
-template <int N, int T, int DIR, int NS, int BUF, class View, int R, int... Rest>
-__device__ __forceinline__ void fft_stages(c32* v, int t, const c32* tw, View b0, View b1) {
+// SB (single buffer): b0 and b1 are the same LDS buffer, so every exchange
+// write first waits for all reads of the previous exchange.
+template <int N, int T, int DIR, int NS, int BUF, bool SB, class View, class Tw, int R, int... Rest>
+__device__ __forceinline__ void fft_stages(c32* v, int t, const Tw& tw, View b0, View b1) {
   constexpr bool last = sizeof...(Rest) == 0;
   const View& out = (BUF == 0) ? b0 : b1;
+  if constexpr (SB && !last) {
+    // the write of this stage happens inside stockham_stage after its
+    // butterflies; the barrier in front of the stage keeps it behind the
+    // previous exchange's reads
+    __syncthreads();
+  }
   stockham_stage<N, T, R, NS, DIR, last>(v, t, tw, out);
   if constexpr (!last) {
     __syncthreads();
     constexpr int E = N / T;
     sfor<E>([&](auto jc) { v[decltype(jc)::value] = out.at(t + T * decltype(jc)::value); });
-    fft_stages<N, T, DIR, NS * R, BUF ^ 1, View, Rest...>(v, t, tw, b0, b1);
+    fft_stages<N, T, DIR, NS * R, BUF ^ 1, SB, View, Tw, Rest...>(v, t, tw, b0, b1);
   }
 }
 
-template <int N, int T, int DIR, int BUF, class View, int... Rs>
-__device__ __forceinline__ void fft_line(c32* v, int t, const c32* tw, View b0, View b1,
+template <int N, int T, int DIR, int BUF, class View, class Tw, int... Rs>
+__device__ __forceinline__ void fft_line(c32* v, int t, const Tw& tw, View b0, View b1,
                                          Radices<Rs...>) {
   static_assert(radix_product(Radices<Rs...>{}) == N, "radices must multiply to N");
-  fft_stages<N, T, DIR, 1, BUF, View, Rs...>(v, t, tw, b0, b1);
+  fft_stages<N, T, DIR, 1, BUF, false, View, Tw, Rs...>(v, t, tw, b0, b1);
 }
+// Single LDS buffer variant (half the LDS, one more barrier per exchange).
+template <int N, int T, int DIR, class View, class Tw, int... Rs>
+__device__ __forceinline__ void fft_line_sb(c32* v, int t, const Tw& tw, View b, Radices<Rs...>) {
+  static_assert(radix_product(Radices<Rs...>{}) == N, "radices must multiply to N");
+  fft_stages<N, T, DIR, 1, 0, true, View, Tw, Rs...>(v, t, tw, b, b);
+}
+template <int N, int T, int DIR, int BUF, class View, int... Rs>
+__device__ __forceinline__ void fft_line(c32* v, int t, const c32* tw, View b0, View b1,
+                                         Radices<Rs...> rad) {
+  fft_line<N, T, DIR, BUF>(v, t, TwTable{tw}, b0, b1, rad);
+}
+
+#ifndef SENSE_TWREG_MAX_E
+#define SENSE_TWREG_MAX_E 8
+#endif
+// Twiddle source of the fused kernels: registers for two-stage transforms
+// with at most 16 elements per thread, the LDS table otherwise.
+template <int N, int T, class Rad>
+struct TwChoice {
+  using type = TwTable;
+  static constexpr bool regs = false;
+};
+template <int N, int T, int R1, int R2>
+struct TwChoice<N, T, Radices<R1, R2>> {
+  static constexpr bool regs = (N / T) <= SENSE_TWREG_MAX_E;
+  using type = std::conditional_t<regs, TwRegs2<N, T, R1, R2>, TwTable>;
+};
 
 // Number of LDS exchanges of one transform.
 template <int... Rs>

@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
   for (int j = 0; j < E; ++j) v[j] = valid ? cscale(load_c<ST_IN>(in, t + T * j), sgn) : c32{0.f, 0.f};
   __syncthreads();
   LineView<1> b0{&buf[0][l * LDL]}, b1{&buf[1][l * LDL]};
-  fft_line<N, T, DIR, 0>(v, t, tw, b0, b1, Rad{});
+  fft_line<N, T, DIR, 0>(v, t, TwTable{tw}, b0, b1, Rad{});
   if (valid) {
     TO* out = static_cast<TO*>(P.out) + off;
     const float s = sgn * P.scale;
@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) col_fwd_ker
   }
   __syncthreads();
   LineView<TX> b0{&buf[0][cx]}, b1{&buf[1][cx]};
-  fft_line<N, T, -1, 0>(u, t, tw, b0, b1, Rad{});
+  fft_line<N, T, -1, 0>(u, t, TwTable{tw}, b0, b1, Rad{});
   if (valid) {
     c32* W = P.w + ((long)b * P.ncoils + c) * N * nx + x;
 #pragma unroll
@@ -186,10 +186,10 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) col_adj_ker
     // the two exchange buffers alternate across coils: an even number of
     // exchanges per coil keeps the start buffer fixed
     if constexpr ((NEX & 1) == 0) {
-      fft_line<N, T, +1, 0>(u, t, tw, b0, b1, Rad{});
+      fft_line<N, T, +1, 0>(u, t, TwTable{tw}, b0, b1, Rad{});
     } else {
-      if (c & 1) fft_line<N, T, +1, 1>(u, t, tw, b0, b1, Rad{});
-      else fft_line<N, T, +1, 0>(u, t, tw, b0, b1, Rad{});
+      if (c & 1) fft_line<N, T, +1, 1>(u, t, TwTable{tw}, b0, b1, Rad{});
+      else fft_line<N, T, +1, 0>(u, t, TwTable{tw}, b0, b1, Rad{});
     }
     const SType* Sc = S + (long)c * N * nx;
 #pragma unroll

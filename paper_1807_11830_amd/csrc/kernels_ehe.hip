@@ -17,6 +17,7 @@
 // segment and the accumulator q stay in registers, and the forward/inverse
 // transforms exchange through LDS only between Stockham stages.  The block
 // also emits its fp64 partial of Re<p, q> for CG.
+#include "bufio.hpp"
 #include "kernels.hpp"
 #include "lengths.hpp"
 #include "reduce.hpp"
@@ -46,16 +47,20 @@ struct EheParams {
 };
 
 template <int N, int ST, bool CG>
-__global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>())
+__global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX)
     ehe2d_kernel(EheParams P) {
-  constexpr int T = Len<N>::T;
-  constexpr int E = Len<N>::E;
-  constexpr int TX = col_tile<T>();
+  constexpr int T = EheLen<N>::T;
+  constexpr int E = EheLen<N>::E;
+  constexpr int TX = EheLen<N>::TX;
   constexpr int NT = T * TX;
-  using Rad = typename Len<N>::R;
+  using Rad = typename EheLen<N>::R;
   constexpr int NEX = exchanges(Rad{});
 
-  __shared__ c32 xbuf[2][N * TX];
+#ifndef SENSE_EHE_SINGLEBUF
+#define SENSE_EHE_SINGLEBUF 1
+#endif
+  constexpr int NBUF = SENSE_EHE_SINGLEBUF ? 1 : 2;
+  __shared__ c32 xbuf[NBUF][N * TX];
   __shared__ c32 tw[N];
   __shared__ float mu[N];
   __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
@@ -98,52 +103,98 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>())
     mu[i] = P.mu[i];
   }
 
-  const long col0 = (long)b * N * nx + x;  // element (b, row 0, x)
+  // Element (row, column) of a batch element's image sits at row * nx + col.
+  // Columns past nx (ragged last tile) read column nx-1 instead of
+  // branching; their results are never stored or reduced.
+  const long nvox = (long)N * nx;
+  const uint32_t xl = (uint32_t)(valid ? x : nx - 1);
+  const uint32_t voff = (uint32_t)t * (uint32_t)nx + xl;  // element offset of row t
+  const uint32_t rstep = (uint32_t)T * (uint32_t)nx;      // rows t -> t + T
+  const uint32_t img_bytes = (uint32_t)(nvox * (long)sizeof(c32));
+  const Buf bq = make_buf(P.q + (long)b * nvox, img_bytes);
   c32 p[E], q[E];
+  {
+    const Buf bp = make_buf(P.p_in + (long)b * nvox, img_bytes);
+    [[maybe_unused]] Buf br, bpo;
+    if constexpr (CG) {
+      br = make_buf(P.r + (long)b * nvox, img_bytes);
+      bpo = make_buf(P.p_out + (long)b * nvox, img_bytes);
+    }
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const long idx = col0 + (long)(t + T * j) * nx;
-    c32 v = {0.f, 0.f};
-    if (valid) {
-      v = P.p_in[idx];
+    for (int j = 0; j < E; ++j) {
+      c32 v = buf_load_c64(bp, voff * 8u, (uint32_t)j * rstep * 8u);
       if constexpr (CG) {
-        const c32 rv = P.r[idx];
+        const c32 rv = buf_load_c64(br, voff * 8u, (uint32_t)j * rstep * 8u);
         v = {(float)((double)rv.re + beta * (double)v.re),
              (float)((double)rv.im + beta * (double)v.im)};
-        P.p_out[idx] = v;
+        if (valid) buf_store_c64(bpo, v, voff * 8u, (uint32_t)j * rstep * 8u);
       }
+      p[j] = v;
+      q[j] = {0.f, 0.f};
     }
-    p[j] = v;
-    q[j] = {0.f, 0.f};
   }
   __syncthreads();
 
-  using SType = typename StorageT<ST>::T;
-  const SType* S = static_cast<const SType*>(P.maps) + (long)b * P.maps_bstride + x;
-  LineView<TX> v0{&xbuf[0][cx]}, v1{&xbuf[1][cx]};
+  using TwC = TwChoice<N, T, Rad>;
+  typename TwC::type twsrc;
+  if constexpr (TwC::regs) twsrc.load(tw, t);
+  else twsrc.tw = tw;
 
-  for (int c = 0; c < P.ncoils; ++c) {
-    const SType* Sc = S + (long)c * N * nx;
-    c32 s[E], u[E];
+  using SType = typename StorageT<ST>::T;
+  const SType* S = static_cast<const SType*>(P.maps) + (long)b * P.maps_bstride;
+  const uint32_t coil_bytes = (uint32_t)(nvox * (long)sizeof(SType));
+  LineView<TX> v0{&xbuf[0][cx]}, v1{&xbuf[NBUF - 1][cx]};
+
+  auto load_s = [&](c32* s, int c) {
+    const Buf bs = make_buf(S + (long)c * nvox, coil_bytes);
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      s[j] = valid ? load_c<ST>(Sc, (long)(t + T * j) * nx) : c32{0.f, 0.f};
-      u[j] = cmul(s[j], p[j]);
-    }
-    fft_line<N, T, -1, 0>(u, t, tw, v0, v1, Rad{});
+    for (int j = 0; j < E; ++j) s[j] = buf_load_st<ST>(bs, voff, (uint32_t)j * rstep);
+  };
+  // One coil: u = S p, forward transform, mask, inverse transform,
+  // q += conj(S) u.  The transform pair uses an even number of exchanges,
+  // so every coil starts on LDS buffer 0.
+  auto coil = [&](const c32* s) {
+    c32 u[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) u[j] = cmul(s[j], p[j]);
+    if constexpr (NBUF == 1) fft_line_sb<N, T, -1>(u, t, twsrc, v0, Rad{});
+    else fft_line<N, T, -1, 0>(u, t, twsrc, v0, v1, Rad{});
 #pragma unroll
     for (int j = 0; j < E; ++j) u[j] = cscale(u[j], mu[t + T * j]);
-    fft_line<N, T, +1, NEX & 1>(u, t, tw, v0, v1, Rad{});
+    if constexpr (NBUF == 1) fft_line_sb<N, T, +1>(u, t, twsrc, v0, Rad{});
+    else fft_line<N, T, +1, NEX & 1>(u, t, twsrc, v0, v1, Rad{});
 #pragma unroll
     for (int j = 0; j < E; ++j) q[j] = cfma_conj(q[j], s[j], u[j]);
+  };
+
+#ifndef SENSE_EHE_PREFETCH
+#define SENSE_EHE_PREFETCH 0
+#endif
+  const int C = P.ncoils;
+#if SENSE_EHE_PREFETCH
+  // Maps of coil c+1 are loaded while coil c is transformed.
+  c32 sc[E], sn[E];
+  load_s(sc, 0);
+  for (int c = 0; c < C; ++c) {
+    if (c + 1 < C) load_s(sn, c + 1);
+    coil(sc);
+#pragma unroll
+    for (int j = 0; j < E; ++j) sc[j] = sn[j];
   }
+#else
+  for (int c = 0; c < C; ++c) {
+    c32 sc[E];
+    load_s(sc, c);
+    coil(sc);
+  }
+#endif
 
   double eta = 0.0;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     c32 qq = {q[j].re + P.lambda * p[j].re, q[j].im + P.lambda * p[j].im};
     if (valid) {
-      P.q[col0 + (long)(t + T * j) * nx] = qq;
+      buf_store_c64(bq, qq, voff * 8u, (uint32_t)j * rstep * 8u);
       eta += (double)p[j].re * (double)qq.re + (double)p[j].im * (double)qq.im;
     }
   }
@@ -157,7 +208,7 @@ int ehe_tile_width(long ny) {
   int tx = 0;
   dispatch_length(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    tx = col_tile<Len<N>::T>();
+    tx = EheLen<N>::TX;
   });
   return tx;
 }
@@ -172,8 +223,8 @@ static hipError_t launch_ehe_impl(const Geom& g, const Tables& tb, EheParams P, 
   P.ncoils = g.ncoils;
   dispatch_length(g.ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    constexpr int T = Len<N>::T;
-    constexpr int TX = col_tile<T>();
+    constexpr int T = EheLen<N>::T;
+    constexpr int TX = EheLen<N>::TX;
     dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)g.batch);
     dim3 block(T * TX);
     switch (g.maps_storage) {

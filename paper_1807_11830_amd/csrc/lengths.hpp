@@ -10,6 +10,12 @@ namespace sense {
 template <int N>
 struct Len;
 
+// Columns per block for column-mode kernels: at least one full wavefront.
+template <int T>
+constexpr int col_tile() {
+  return T >= 4 ? 16 : 32;
+}
+
 #define SENSE_LEN(N_, T_, ...)                 \
   template <>                                  \
   struct Len<N_> {                             \
@@ -32,6 +38,53 @@ SENSE_LEN(256, 16, 16, 16)
 SENSE_LEN(320, 16, 20, 4, 4)
 SENSE_LEN(384, 16, 24, 4, 4)
 #undef SENSE_LEN
+
+// Configuration of the fused E^H E kernel along y: threads per column T,
+// radix list, columns per block TX.  Fewer elements per thread than the
+// generic configuration where that buys occupancy (the kernel keeps p, q,
+// two sets of maps and the working column in registers).
+template <int N>
+struct EheLen : Len<N> {
+  static constexpr int TX = col_tile<Len<N>::T>();
+};
+
+#ifndef SENSE_EHE256_T
+#define SENSE_EHE256_T 16
+#endif
+#ifndef SENSE_EHE_TX
+#define SENSE_EHE_TX 16
+#endif
+#if SENSE_EHE256_T == 32
+template <>
+struct EheLen<256> {
+  static constexpr int T = 32;
+  static constexpr int E = 8;
+  using R = Radices<8, 8, 4>;
+  static constexpr int TX = 16;
+};
+#else
+template <>
+struct EheLen<256> {
+  static constexpr int T = 16;
+  static constexpr int E = 16;
+  using R = Radices<16, 16>;
+  static constexpr int TX = SENSE_EHE_TX;
+};
+#endif
+template <>
+struct EheLen<128> {
+  static constexpr int T = 16;
+  static constexpr int E = 8;
+  using R = Radices<8, 4, 4>;
+  static constexpr int TX = 16;
+};
+template <>
+struct EheLen<192> {
+  static constexpr int T = 16;
+  static constexpr int E = 12;
+  using R = Radices<12, 4, 4>;
+  static constexpr int TX = 16;
+};
 
 // Calls f(std::integral_constant<int, N>) for the runtime length n; returns
 // false when n is not instantiated.
@@ -61,10 +114,5 @@ inline bool dispatch_length(long n, F&& f) {
   }
 }
 
-// Columns per block for column-mode kernels: at least one full wavefront.
-template <int T>
-constexpr int col_tile() {
-  return T >= 4 ? 16 : 32;
-}
 
 }  // namespace sense

@@ -87,6 +87,9 @@ static sense_status validate_desc(const sense_desc* d) {
   if (!length_supported(d->ny))
     return fail(SENSE_ERR_UNSUPPORTED, "ny=" + std::to_string(d->ny) + " is not a supported transform length");
   if (d->batch > 65535 || d->ncoils > 65535) return fail(SENSE_ERR_UNSUPPORTED, "batch and coils must be <= 65535");
+  // one image (or one coil image) is addressed with 32-bit byte offsets
+  if ((double)d->nx * d->ny * d->nz * 8.0 > 2147483647.0)
+    return fail(SENSE_ERR_UNSUPPORTED, "one image must be below 2^31 bytes");
   const double elems = (double)d->nx * d->ny * d->nz * d->ncoils * d->batch;
   if (elems > 4.0e12) return fail(SENSE_ERR_UNSUPPORTED, "problem too large");
   return SENSE_OK;
@@ -156,7 +159,7 @@ static sense_status timed_ehe_begin(sense_plan p, hipStream_t st, hipEvent_t* st
     p->events.emplace_back(a, b);
   }
   auto& pr = p->events[p->events_used++];
-  hipEventRecord(pr.first, st);
+  if (hipEventRecord(pr.first, st) != hipSuccess) return fail(SENSE_ERR_DEVICE, "hipEventRecord failed");
   *stop = pr.second;
   return SENSE_OK;
 }
@@ -245,7 +248,7 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
     up(p->L.rows_u, ru.data(), ru.size() * sizeof(int32_t));
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
-      hipFree(p->mem);
+      (void)hipFree(p->mem);
       delete p;
       return device_fail(e, "table upload");
     }
@@ -267,12 +270,12 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
 
 sense_status sense_plan_destroy(sense_plan p) {
   if (!p) return fail(SENSE_ERR_INVALID, "plan is NULL");
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   for (auto& pr : p->events) {
-    hipEventDestroy(pr.first);
-    hipEventDestroy(pr.second);
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
   }
-  hipFree(p->mem);
+  (void)hipFree(p->mem);
   delete p;
   return SENSE_OK;
 }
@@ -318,7 +321,7 @@ sense_status sense_apply_EHE(sense_plan p, const void* d_p, void* d_q, double la
   if (s != SENSE_OK) return s;
   hipError_t e = launch_ehe(p->g, p->tb, p->maps, static_cast<const c32*>(d_p), static_cast<c32*>(d_q),
                             (float)lambda, p->at<double>(p->L.eta_part), st);
-  if (stop) hipEventRecord(stop, st);
+  if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
   return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_apply_EHE launch");
 }
 
@@ -352,7 +355,7 @@ sense_status sense_cg_solve(sense_plan p, const void* d_y, void* d_x, int32_t ma
     s = timed_ehe_begin(p, st, &stop);
     if (s != SENSE_OK) return s;
     e = launch_ehe_cg(p->g, p->tb, p->maps, r, pv, q, (float)lambda, cg, st);
-    if (stop) hipEventRecord(stop, st);
+    if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
     if (e == hipSuccess) e = launch_cg_update(p->g, x, r, pv, q, cg, st);
   }
   CgInfo* info = p->at<CgInfo>(p->L.info);
