@@ -26,6 +26,34 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
+# HBM traffic of the fused kernel comes from rocprofv3 FETCH_SIZE/WRITE_SIZE
+# runs recorded under profiles/; it is reported only while the kernel sources
+# still hash to what was measured.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cgsense_256x256_c12_b160_k30.traffic.json")
+EHE_SOURCES = ["kernels_ehe.hip", "fft_engine.hpp", "dft_small.hpp", "cplx.hpp", "bufio.hpp",
+               "lengths.hpp", "reduce.hpp", "kernels.hpp", "cg_scalar.hpp"]
+
+
+def measured_traffic(kernel_key):
+    import hashlib
+
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for name in rec.get("kernel_sources", EHE_SOURCES):
+        path = os.path.join(ROOT, "paper_1807_11830_amd", "csrc", name)
+        if os.path.exists(path):
+            h.update(name.encode())
+            with open(path, "rb") as f:
+                h.update(f.read())
+    if h.hexdigest() != rec.get("kernel_sources_sha256"):
+        return None
+    k = rec.get("kernels", {}).get(kernel_key)
+    return None if k is None else k["traffic_bytes"]
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -178,7 +206,8 @@ def main():
                    "inner_products": "f64", "nx": w.n, "ny": w.n, "coils": C},
         "roofline": {"bound": "hbm", "kernel": "ehe2d_kernel (fused E^H E + p update, CG mode)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("sense::ehe2d_kernel<256, 0, true>"),
                      "avg_launch_us": avg_s * 1e6, "launches": n_l,
                      "bytes_per_launch": bytes_launch},
         "ehe_apply": {"avg_launch_us": apply_s * 1e6, "bytes_per_launch": apply_bytes,

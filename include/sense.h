@@ -118,9 +118,10 @@ SENSE_API size_t sense_plan_device_bytes(const sense_desc* desc);
  *           DC at index (Nz/2, Ny/2)); nonzero = sampled.  Copied.
  *   stream  stream used for the table uploads (synchronised before return).
  *   out     receives the plan.
- * Supported: ndim = 2 (3 reported UNSUPPORTED for now); Ny and Nx from
- * {8, 16, 32, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384}; the normal
- * operator alone accepts any Nx >= 1.  Other sizes -> SENSE_ERR_UNSUPPORTED.
+ * Supported: ndim = 2 or 3; Ny (and Nz in 3D) from {8, 16, 32, 48, 64, 80,
+ * 96, 128, 160, 192, 256, 320, 384}; Nx from the same set for E, E^H and
+ * CG, while the normal operator alone accepts any Nx >= 1; one image must
+ * be below 2^31 bytes.  Other sizes -> SENSE_ERR_UNSUPPORTED.
  */
 SENSE_API sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const uint8_t* h_mask,
                                void* stream, sense_plan* out);

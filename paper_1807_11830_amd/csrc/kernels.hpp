@@ -91,11 +91,18 @@ hipError_t launch_cg_init(const Geom& g, const c32* b, c32* x, c32* r, c32* p,
 hipError_t launch_cg_update(const Geom& g, c32* x, c32* r, const c32* p, const c32* q,
                             const CgArgs& cg, hipStream_t st);
 hipError_t launch_cg_finish(const Geom& g, const CgArgs& cg, CgInfo* info, hipStream_t st);
+hipError_t launch_cg_pupdate(const Geom& g, const c32* r, c32* p, const CgArgs& cg, hipStream_t st);
 
 // Full-grid forward and adjoint operators (2D).
 hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32* x, c32* work,
                     void* y, hipStream_t st);
 hipError_t launch_EH(const Geom& g, const Tables& tb, const void* maps, const void* y, c32* work,
                      c32* x, hipStream_t st);
+// Normal operator from column passes (3D): q = E^H E p + lambda p, with the
+// readout transforms cancelled; fp64 partials of Re<p, q> per block.
+hipError_t launch_EHE_composed(const Geom& g, const Tables& tb, const void* maps, const c32* p, c32* q,
+                               c32* work, float lambda, double* eta_part, hipStream_t st);
+// Blocks of the last composed pass per batch element (partials count).
+int adj_tiles(long nx, long ny, long nz);
 
 }  // namespace sense

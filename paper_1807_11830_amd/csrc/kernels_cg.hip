@@ -11,6 +11,7 @@
 // vectors are fp32 complex.  Every block of a batch element reduces the same
 // partials in the same order, so all blocks take the same decisions and the
 // results do not depend on scheduling.
+#include "cg_scalar.hpp"
 #include "kernels.hpp"
 #include "reduce.hpp"
 
@@ -138,6 +139,39 @@ __global__ void cg_finish_kernel(CgArgs cg, CgInfo* info) {
     o.rho_final = rho_final;
     info[b] = o;
   }
+}
+
+// p = r + beta p with the start-of-iteration scalar logic (used where the
+// normal operator is not the fused 2D kernel).
+__global__ void __launch_bounds__(CG_NT) cg_pupdate_kernel(const c32* __restrict__ r, c32* __restrict__ p,
+                                                           long nvox, CgArgs cg) {
+  const int b = blockIdx.y;
+  double beta = 0.0;
+  if (!cg_iteration_begin(cg.state + b, cg.rr_part, cg.rr_tiles, cg.rho_hist, cg.hist_len, cg.tol, b,
+                          blockIdx.x == 0 && threadIdx.x == 0, beta))
+    return;
+  const long base = (long)b * nvox + (long)blockIdx.x * CG_CHUNK;
+  const long lim = (long)b * nvox + nvox;
+#pragma unroll
+  for (int s = 0; s < CG_STEPS; ++s) {
+    const long i = base + ((long)s * CG_NT + threadIdx.x) * CG_VEC;
+    if (i < lim) {
+      const c32x2 rv = *reinterpret_cast<const c32x2*>(r + i);
+      c32x2 pv = *reinterpret_cast<const c32x2*>(p + i);
+      pv.a.re = (float)((double)rv.a.re + beta * pv.a.re);
+      pv.a.im = (float)((double)rv.a.im + beta * pv.a.im);
+      pv.b.re = (float)((double)rv.b.re + beta * pv.b.re);
+      pv.b.im = (float)((double)rv.b.im + beta * pv.b.im);
+      *reinterpret_cast<c32x2*>(p + i) = pv;
+    }
+  }
+}
+
+hipError_t launch_cg_pupdate(const Geom& g, const c32* r, c32* p, const CgArgs& cg, hipStream_t st) {
+  const long nvox = g.nx * g.ny * g.nz;
+  dim3 grid((unsigned)cg_tiles(nvox), (unsigned)g.batch);
+  hipLaunchKernelGGL(cg_pupdate_kernel, grid, dim3(CG_NT), 0, st, r, p, nvox, cg);
+  return hipGetLastError();
 }
 
 hipError_t launch_cg_init(const Geom& g, const c32* bvec, c32* x, c32* r, c32* p, const CgArgs& cg,

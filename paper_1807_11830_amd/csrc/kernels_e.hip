@@ -20,8 +20,10 @@
 //        row pass     y = scale * F_x( W )               (sampled rows; others zero)
 //   E^H: row pass     W = F_x^H( y )                     (sampled rows only)
 //        column pass  x = scale * sum_c conj(S_c) .* F_y^H( mask_y(W_c) )
+#include "bufio.hpp"
 #include "kernels.hpp"
 #include "lengths.hpp"
+#include "reduce.hpp"
 
 #include <cmath>
 
@@ -94,114 +96,156 @@ __global__ void zero_rows_kernel(void* out, const int32_t* rows, int nrows, long
   for (long i = threadIdx.x; i < nx; i += blockDim.x) store_c<ST>(o, i, c32{0.f, 0.f});
 }
 
-struct ColParams {
+// Column passes: transforms along y (element stride nx) or z (stride nx*ny)
+// for TX adjacent x columns per block.  Modes:
+//   FWD_COIL  u = S_c .* X, forward transform, optional mask, store W[b][c]
+//   FWD       forward transform of W in place, optional mask
+//   ADJ       optional masked load, inverse transform of W in place
+//   ADJ_COIL  for every coil: optional masked load of W[b][c], inverse
+//             transform, accumulate conj(S_c) .* u; store X[b] (+ lambda p,
+//             fp64 partial Re<p, X> for CG)
+//   PROJ      F^H diag(M) F of W in place along z (the (ky, kz) mask of the
+//             current ky plane): the middle of the 3D normal operator
+enum ColMode : int { CM_FWD_COIL = 0, CM_FWD = 1, CM_ADJ = 2, CM_ADJ_COIL = 3, CM_PROJ = 4 };
+
+struct ColPass {
   const void* maps;
-  const c32* x;       // E: image
-  c32* w;             // workspace
-  c32* xout;          // E^H: image
-  const uint8_t* mask;
+  const c32* src;
+  c32* dst;
+  const c32* addp;     // ADJ_COIL: p for lambda p and eta (may be null)
+  double* eta_part;    // ADJ_COIL: [b][gridDim.x * gridDim.y] (may be null)
+  const uint8_t* mask; // centred [nz][ny]
   const c32* tw;
-  long nx;
+  long nx, ny, nz;
   long maps_bstride;
   int ncoils;
+  int mask_store;
+  int mask_load;
   float scale;
+  float lambda;
 };
 
-// E column pass: one block per (x tile, coil, batch element).
-template <int N, int ST>
-__global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) col_fwd_kernel(ColParams P) {
+template <int N, int AXIS, int MODE, int ST>
+__global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) colpass_kernel(ColPass P) {
   constexpr int T = Len<N>::T;
   constexpr int E = Len<N>::E;
   constexpr int TX = col_tile<T>();
   constexpr int NT = T * TX;
   using Rad = typename Len<N>::R;
-  __shared__ c32 buf[2][N * TX];
+  __shared__ c32 buf[N * TX];
   __shared__ c32 tw[N];
-  const int tid = threadIdx.x, cx = tid % TX, t = tid / TX;
-  const long x = (long)blockIdx.x * TX + cx;
-  const int c = blockIdx.y, b = blockIdx.z;
-  const bool valid = x < P.nx;
-  const long nx = P.nx;
-  for (int i = tid; i < N; i += NT) tw[i] = P.tw[i];
+  __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
 
-  using SType = typename StorageT<ST>::T;
-  const SType* S = static_cast<const SType*>(P.maps) + (long)b * P.maps_bstride + (long)c * N * nx + x;
-  const c32* X = P.x + (long)b * N * nx + x;
-  const float sgn = (t & 1) ? -1.f : 1.f;
-  c32 u[E];
-#pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const long o = (long)(t + T * j) * nx;
-    u[j] = valid ? cscale(cmul(load_c<ST>(S, o), X[o]), sgn) : c32{0.f, 0.f};
-  }
-  __syncthreads();
-  LineView<TX> b0{&buf[0][cx]}, b1{&buf[1][cx]};
-  fft_line<N, T, -1, 0>(u, t, TwTable{tw}, b0, b1, Rad{});
-  if (valid) {
-    c32* W = P.w + ((long)b * P.ncoils + c) * N * nx + x;
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int k = t + T * j;
-      if (P.mask[k]) W[(long)k * nx] = cscale(u[j], sgn);
-    }
-  }
-}
-
-// E^H column pass: one block per (x tile, batch element), coils summed in
-// increasing order in registers.
-template <int N, int ST>
-__global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) col_adj_kernel(ColParams P) {
-  constexpr int T = Len<N>::T;
-  constexpr int E = Len<N>::E;
-  constexpr int TX = col_tile<T>();
-  constexpr int NT = T * TX;
-  constexpr int NEX = exchanges(typename Len<N>::R{});
-  using Rad = typename Len<N>::R;
-  __shared__ c32 buf[2][N * TX];
-  __shared__ c32 tw[N];
   const int tid = threadIdx.x, cx = tid % TX, t = tid / TX;
+  const long nx = P.nx, ny = P.ny;
   const long x = (long)blockIdx.x * TX + cx;
-  const int b = blockIdx.y;
-  const bool valid = x < P.nx;
-  const long nx = P.nx;
+  const bool valid = x < nx;
+  const uint32_t xl = (uint32_t)(valid ? x : nx - 1);
+  const long pl = blockIdx.y;  // z for AXIS 1, y for AXIS 2
+  const long nvox = nx * ny * P.nz;
+  const uint32_t es = (uint32_t)(AXIS == 1 ? nx : nx * ny);
+  const uint32_t lbase = (uint32_t)(AXIS == 1 ? pl * ny * nx : pl * nx) + xl;
+  const uint32_t voff = lbase + (uint32_t)t * es;
+  const uint32_t rstep = (uint32_t)T * es;
+  const uint32_t vbytes = (uint32_t)(nvox * 8);
+  auto mask_at = [&](int k) -> bool {
+    return AXIS == 1 ? P.mask[pl * ny + k] != 0 : P.mask[(long)k * ny + pl] != 0;
+  };
   for (int i = tid; i < N; i += NT) tw[i] = P.tw[i];
   __syncthreads();
 
   using SType = typename StorageT<ST>::T;
-  const SType* S = static_cast<const SType*>(P.maps) + (long)b * P.maps_bstride + x;
-  const c32* W = P.w + (long)b * P.ncoils * N * nx + x;
   const float sgn = (t & 1) ? -1.f : 1.f;
-  LineView<TX> b0{&buf[0][cx]}, b1{&buf[1][cx]};
-  c32 acc[E];
-#pragma unroll
-  for (int j = 0; j < E; ++j) acc[j] = {0.f, 0.f};
-  for (int c = 0; c < P.ncoils; ++c) {
-    const c32* Wc = W + (long)c * N * nx;
+  LineView<TX> lv{&buf[cx]};
+  const TwTable twt{tw};
+
+  if constexpr (MODE != CM_ADJ_COIL) {
+    const long bc = blockIdx.z;
+    const long b = bc / P.ncoils, c = bc % P.ncoils;
     c32 u[E];
+    if constexpr (MODE == CM_FWD_COIL) {
+      const Buf bs = make_buf(static_cast<const SType*>(P.maps) + b * P.maps_bstride + c * nvox,
+                              (uint32_t)(nvox * sizeof(SType)));
+      const Buf bx = make_buf(P.src + b * nvox, vbytes);
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int k = t + T * j;
-      u[j] = (valid && P.mask[k]) ? cscale(Wc[(long)k * nx], sgn) : c32{0.f, 0.f};
-    }
-    // the two exchange buffers alternate across coils: an even number of
-    // exchanges per coil keeps the start buffer fixed
-    if constexpr ((NEX & 1) == 0) {
-      fft_line<N, T, +1, 0>(u, t, TwTable{tw}, b0, b1, Rad{});
+      for (int j = 0; j < E; ++j) {
+        const uint32_t o = voff + (uint32_t)j * rstep;
+        u[j] = cscale(cmul(buf_load_st<ST>(bs, o, 0), buf_load_c64(bx, o * 8u, 0)), sgn);
+      }
     } else {
-      if (c & 1) fft_line<N, T, +1, 1>(u, t, TwTable{tw}, b0, b1, Rad{});
-      else fft_line<N, T, +1, 0>(u, t, TwTable{tw}, b0, b1, Rad{});
+      const Buf bw = make_buf(P.src + bc * nvox, vbytes);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const bool on = MODE == CM_ADJ && P.mask_load ? mask_at(t + T * j) : true;
+        const c32 v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
+        u[j] = on ? cscale(v, sgn) : c32{0.f, 0.f};
+      }
     }
-    const SType* Sc = S + (long)c * N * nx;
+    if constexpr (MODE == CM_ADJ) {
+      fft_line_sb<N, T, +1>(u, t, twt, lv, Rad{});
+    } else if constexpr (MODE == CM_PROJ) {
+      static_assert(AXIS == 2, "the projector runs along z");
+      fft_line_sb<N, T, -1>(u, t, twt, lv, Rad{});
+      // checkerboards of the forward output and inverse input cancel
+#pragma unroll
+      for (int j = 0; j < E; ++j)
+        if (!mask_at(t + T * j)) u[j] = {0.f, 0.f};
+      fft_line_sb<N, T, +1>(u, t, twt, lv, Rad{});
+    } else {
+      fft_line_sb<N, T, -1>(u, t, twt, lv, Rad{});
+    }
+    if (valid) {
+      const Buf bd = make_buf(P.dst + bc * nvox, vbytes);
+      const float sc = sgn * P.scale;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const bool on = (MODE == CM_FWD_COIL || MODE == CM_FWD) && P.mask_store ? mask_at(t + T * j) : true;
+        if (on) buf_store_c64(bd, cscale(u[j], sc), (voff + (uint32_t)j * rstep) * 8u, 0);
+      }
+    }
+  } else {
+    const long b = blockIdx.z;
+    c32 acc[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) acc[j] = {0.f, 0.f};
+    for (int c = 0; c < P.ncoils; ++c) {
+      const Buf bw = make_buf(P.src + (b * P.ncoils + c) * nvox, vbytes);
+      c32 u[E];
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const bool on = P.mask_load ? mask_at(t + T * j) : true;
+        const c32 v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
+        u[j] = on ? cscale(v, sgn) : c32{0.f, 0.f};
+      }
+      fft_line_sb<N, T, +1>(u, t, twt, lv, Rad{});
+      const Buf bs = make_buf(static_cast<const SType*>(P.maps) + b * P.maps_bstride + (long)c * nvox,
+                              (uint32_t)(nvox * sizeof(SType)));
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const c32 sv = buf_load_st<ST>(bs, voff + (uint32_t)j * rstep, 0);
+        acc[j] = cfma_conj(acc[j], sv, cscale(u[j], sgn));
+      }
+    }
+    const Buf bd = make_buf(P.dst + b * nvox, vbytes);
+    double eta = 0.0;
+    [[maybe_unused]] Buf bp;
+    if (P.addp) bp = make_buf(P.addp + b * nvox, vbytes);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const c32 s = valid ? load_c<ST>(Sc, (long)(t + T * j) * nx) : c32{0.f, 0.f};
-      acc[j] = cfma_conj(acc[j], s, cscale(u[j], sgn));
+      const uint32_t o = (voff + (uint32_t)j * rstep) * 8u;
+      c32 qq = cscale(acc[j], P.scale);
+      if (P.addp) {
+        const c32 pv = buf_load_c64(bp, o, 0);
+        qq = {qq.re + P.lambda * pv.re, qq.im + P.lambda * pv.im};
+        eta += (double)pv.re * (double)qq.re + (double)pv.im * (double)qq.im;
+      }
+      if (valid) buf_store_c64(bd, qq, o, 0);
     }
-  }
-  if (valid) {
-    c32* X = P.xout + (long)b * N * nx + x;
-#pragma unroll
-    for (int j = 0; j < E; ++j) X[(long)(t + T * j) * nx] = cscale(acc[j], P.scale);
+    if (P.eta_part) {
+      if (!valid) eta = 0.0;
+      const double tot = block_sum<NT>(eta, red);
+      if (tid == 0) P.eta_part[b * (long)gridDim.x * gridDim.y + (long)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    }
   }
 }
 
@@ -244,60 +288,72 @@ static hipError_t launch_zero_rows(const Geom& g, void* out, const int32_t* rows
   return hipGetLastError();
 }
 
-// (-1)^(nx/2 + ny/2) / sqrt(nx ny): the global factor of the centred unitary
-// 2D transform in checkerboard form (both directions).
-static float centred_scale(long nx, long ny) {
-  const long h = (nx / 2 + ny / 2) & 1;
-  return (float)((h ? -1.0 : 1.0) / std::sqrt((double)nx * (double)ny));
+
+// (-1)^(n/2) / sqrt(n): the global factor of one centred unitary axis
+// transform in checkerboard form (both directions); 1 for an absent axis.
+static double axis_scale(long n) {
+  if (n <= 1) return 1.0;
+  return (((n / 2) & 1) ? -1.0 : 1.0) / std::sqrt((double)n);
 }
 
-template <int STM>
-static hipError_t launch_col_fwd(const Geom& g, ColParams P, hipStream_t st) {
+template <int AXIS, int MODE>
+static hipError_t launch_colpass(const Geom& g, ColPass P, long n, hipStream_t st) {
   hipError_t err = hipErrorInvalidValue;
-  dispatch_length(g.ny, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    constexpr int TX = col_tile<Len<N>::T>();
-    dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)g.ncoils, (unsigned)g.batch);
-    hipLaunchKernelGGL((col_fwd_kernel<N, STM>), grid, dim3(Len<N>::T * TX), 0, st, P);
-    err = hipGetLastError();
-  });
-  return err;
-}
-
-template <int STM>
-static hipError_t launch_col_adj(const Geom& g, ColParams P, hipStream_t st) {
-  hipError_t err = hipErrorInvalidValue;
-  dispatch_length(g.ny, [&](auto nc) {
-    constexpr int N = decltype(nc)::value;
-    constexpr int TX = col_tile<Len<N>::T>();
-    dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)g.batch);
-    hipLaunchKernelGGL((col_adj_kernel<N, STM>), grid, dim3(Len<N>::T * TX), 0, st, P);
-    err = hipGetLastError();
-  });
-  return err;
-}
-
-hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32* x, c32* work,
-                    void* y, hipStream_t st) {
-  if (g.nz != 1) return hipErrorInvalidValue;
-  ColParams P{};
-  P.maps = maps;
-  P.x = x;
-  P.w = work;
-  P.mask = tb.mask_c;
-  P.tw = tb.tw_y;
   P.nx = g.nx;
+  P.ny = g.ny;
+  P.nz = g.nz;
   P.maps_bstride = g.maps_bstride;
   P.ncoils = g.ncoils;
+  dispatch_length(n, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    constexpr int TX = col_tile<Len<N>::T>();
+    const long planes = AXIS == 1 ? g.nz : g.ny;
+    const long zdim = MODE == CM_ADJ_COIL ? g.batch : (long)g.batch * g.ncoils;
+    dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)planes, (unsigned)zdim);
+    dim3 block(Len<N>::T * TX);
+    switch (g.maps_storage) {
+      case ST_C64: hipLaunchKernelGGL((colpass_kernel<N, AXIS, MODE, ST_C64>), grid, block, 0, st, P); break;
+      case ST_BF16: hipLaunchKernelGGL((colpass_kernel<N, AXIS, MODE, ST_BF16>), grid, block, 0, st, P); break;
+      case ST_FP16: hipLaunchKernelGGL((colpass_kernel<N, AXIS, MODE, ST_FP16>), grid, block, 0, st, P); break;
+      default: return;
+    }
+    err = hipGetLastError();
+  });
+  return err;
+}
+
+int adj_tiles(long nx, long ny, long nz) {
+  int tx = 0;
+  dispatch_length(ny, [&](auto nc) { tx = col_tile<Len<decltype(nc)::value>::T>(); });
+  return tx ? (int)(((nx + tx - 1) / tx) * nz) : 0;
+}
+
+// E x -> y, through the workspace W:  y-pass (coil product), z-pass (3D),
+// x rows of the sampled (kz, ky) lines, zeros elsewhere.
+hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32* x, c32* work,
+                    void* y, hipStream_t st) {
+  const bool is3d = g.nz > 1;
+  ColPass P{};
+  P.maps = maps;
+  P.src = x;
+  P.dst = work;
+  P.mask = tb.mask_c;
+  P.tw = tb.tw_y;
+  P.mask_store = is3d ? 0 : 1;
   P.scale = 1.f;
-  hipError_t err = hipErrorInvalidValue;
-  switch (g.maps_storage) {
-    case ST_C64: err = launch_col_fwd<ST_C64>(g, P, st); break;
-    case ST_BF16: err = launch_col_fwd<ST_BF16>(g, P, st); break;
-    case ST_FP16: err = launch_col_fwd<ST_FP16>(g, P, st); break;
+  hipError_t err = launch_colpass<1, CM_FWD_COIL>(g, P, g.ny, st);
+  if (err == hipSuccess && is3d) {
+    ColPass Z{};
+    Z.src = work;
+    Z.dst = work;
+    Z.mask = tb.mask_c;
+    Z.tw = tb.tw_z;
+    Z.mask_store = 1;
+    Z.scale = 1.f;
+    err = launch_colpass<2, CM_FWD>(g, Z, g.nz, st);
   }
   if (err != hipSuccess) return err;
-  const float sc = centred_scale(g.nx, g.ny);
+  const float sc = (float)(axis_scale(g.nx) * axis_scale(g.ny) * axis_scale(g.nz));
   switch (g.kspace_storage) {
     case ST_C64:
       err = launch_rows<-1, ST_C64, ST_C64>(g, tb.tw_x, work, y, tb.rows_s, tb.n_rows_s, sc, st);
@@ -316,9 +372,39 @@ hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32
   return err;
 }
 
+// The adjoint passes after the x rows: z-pass (3D, masked loads) and the
+// y-pass with the conjugate-sensitivity coil sum into x.
+static hipError_t launch_EH_tail(const Geom& g, const Tables& tb, const void* maps, c32* work, c32* x,
+                                 const c32* addp, float lambda, double* eta_part, hipStream_t st) {
+  const bool is3d = g.nz > 1;
+  hipError_t err = hipSuccess;
+  if (is3d) {
+    ColPass Z{};
+    Z.src = work;
+    Z.dst = work;
+    Z.mask = tb.mask_c;
+    Z.tw = tb.tw_z;
+    Z.mask_load = 1;
+    Z.scale = 1.f;
+    err = launch_colpass<2, CM_ADJ>(g, Z, g.nz, st);
+    if (err != hipSuccess) return err;
+  }
+  ColPass P{};
+  P.maps = maps;
+  P.src = work;
+  P.dst = x;
+  P.addp = addp;
+  P.lambda = lambda;
+  P.eta_part = eta_part;
+  P.mask = tb.mask_c;
+  P.tw = tb.tw_y;
+  P.mask_load = is3d ? 0 : 1;
+  P.scale = (float)(axis_scale(g.nx) * axis_scale(g.ny) * axis_scale(g.nz));
+  return launch_colpass<1, CM_ADJ_COIL>(g, P, g.ny, st);
+}
+
 hipError_t launch_EH(const Geom& g, const Tables& tb, const void* maps, const void* y, c32* work,
                      c32* x, hipStream_t st) {
-  if (g.nz != 1) return hipErrorInvalidValue;
   hipError_t err = hipErrorInvalidValue;
   switch (g.kspace_storage) {
     case ST_C64: err = launch_rows<+1, ST_C64, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st); break;
@@ -326,22 +412,48 @@ hipError_t launch_EH(const Geom& g, const Tables& tb, const void* maps, const vo
     case ST_FP16: err = launch_rows<+1, ST_FP16, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st); break;
   }
   if (err != hipSuccess) return err;
-  ColParams P{};
+  return launch_EH_tail(g, tb, maps, work, x, nullptr, 0.f, nullptr, st);
+}
+
+// Normal operator from column passes (3D).  With a (ky, kz) mask the
+// readout transforms cancel (F_x^H F_x = I), so
+//   q = sum_c conj(S_c) .* F_y^H [ F_z^H diag(M) F_z ] F_y (S_c .* p) + lambda p
+// as three passes: y forward with the coil product, the z projector per
+// (ky, x) line, y inverse with the conjugate-sensitivity coil sum.  Each
+// centred axis pair contributes 1/n, applied once: scale 1/(ny nz).
+hipError_t launch_EHE_composed(const Geom& g, const Tables& tb, const void* maps, const c32* p, c32* q,
+                               c32* work, float lambda, double* eta_part, hipStream_t st) {
+  ColPass P{};
   P.maps = maps;
-  P.w = work;
-  P.xout = x;
+  P.src = p;
+  P.dst = work;
   P.mask = tb.mask_c;
   P.tw = tb.tw_y;
-  P.nx = g.nx;
-  P.maps_bstride = g.maps_bstride;
-  P.ncoils = g.ncoils;
-  P.scale = centred_scale(g.nx, g.ny);
-  switch (g.maps_storage) {
-    case ST_C64: return launch_col_adj<ST_C64>(g, P, st);
-    case ST_BF16: return launch_col_adj<ST_BF16>(g, P, st);
-    case ST_FP16: return launch_col_adj<ST_FP16>(g, P, st);
+  P.mask_store = g.nz > 1 ? 0 : 1;
+  P.scale = 1.f;
+  hipError_t err = launch_colpass<1, CM_FWD_COIL>(g, P, g.ny, st);
+  if (err == hipSuccess && g.nz > 1) {
+    ColPass Z{};
+    Z.src = work;
+    Z.dst = work;
+    Z.mask = tb.mask_c;
+    Z.tw = tb.tw_z;
+    Z.scale = 1.f;
+    err = launch_colpass<2, CM_PROJ>(g, Z, g.nz, st);
   }
-  return hipErrorInvalidValue;
+  if (err != hipSuccess) return err;
+  ColPass A{};
+  A.maps = maps;
+  A.src = work;
+  A.dst = q;
+  A.addp = p;
+  A.lambda = lambda;
+  A.eta_part = eta_part;
+  A.mask = tb.mask_c;
+  A.tw = tb.tw_y;
+  A.mask_load = g.nz > 1 ? 0 : 1;
+  A.scale = (float)(1.0 / ((double)g.ny * (double)g.nz));
+  return launch_colpass<1, CM_ADJ_COIL>(g, A, g.ny, st);
 }
 
 }  // namespace sense

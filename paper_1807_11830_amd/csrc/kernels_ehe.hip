@@ -18,6 +18,7 @@
 // transforms exchange through LDS only between Stockham stages.  The block
 // also emits its fp64 partial of Re<p, q> for CG.
 #include "bufio.hpp"
+#include "cg_scalar.hpp"
 #include "kernels.hpp"
 #include "lengths.hpp"
 #include "reduce.hpp"
@@ -76,26 +77,9 @@ __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX)
 
   double beta = 0.0;
   if constexpr (CG) {
-    // Every block of batch element b derives the same scalars from the same
-    // partials in the same order, so no grid-wide synchronisation is needed.
-    CgState* st = P.state + b;
-    if (st->status != CG_RUNNING) return;
-    const int k = st->iter;
-    const double rho = ordered_sum(P.rr_part + (long)b * P.rr_tiles, P.rr_tiles);
-    const double rho0 = (k == 0) ? rho : st->rho0;
-    int stop = CG_RUNNING;
-    if (!finite64(rho)) stop = CG_NONFINITE;
-    else if (k > 0 && P.tol > 0.0 && sqrt(rho / rho0) < P.tol) stop = CG_CONVERGED;
-    else if (rho == 0.0) stop = CG_EXACT;
-    if (tile == 0 && tid == 0) {
-      if (k == 0) st->rho0 = rho;
-      st->rho[k & 1] = rho;
-      st->rho_cur = rho;
-      if (P.rho_hist && k < P.hist_len) P.rho_hist[(long)b * P.hist_len + k] = rho;
-      if (stop != CG_RUNNING) st->status = stop;
-    }
-    if (stop != CG_RUNNING) return;
-    if (k > 0) beta = rho / st->rho[(k - 1) & 1];
+    if (!cg_iteration_begin(P.state + b, P.rr_part, P.rr_tiles, P.rho_hist, P.hist_len, P.tol, b,
+                            tile == 0 && tid == 0, beta))
+      return;
   }
 
   for (int i = tid; i < N; i += NT) {

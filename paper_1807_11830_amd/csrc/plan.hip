@@ -36,7 +36,7 @@ static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 static size_t storage_bytes(int st) { return st == ST_C64 ? 8 : 4; }
 
 struct Layout {
-  size_t tw_x, tw_y, mu_y, mask_c, rows_s, rows_u;
+  size_t tw_x, tw_y, tw_z, mu_y, mask_c, rows_s, rows_u;
   size_t work, r, p, q;
   size_t state, eta_part, rr_part, info;
   size_t total;
@@ -47,8 +47,12 @@ static Layout make_layout(const sense_desc& d) {
   Layout L{};
   const size_t nvox = (size_t)d.nx * d.ny * d.nz;
   const size_t B = (size_t)d.batch, C = (size_t)d.ncoils;
-  const int tx = ehe_tile_width(d.ny);
-  L.eta_tiles = (int)((d.nx + tx - 1) / tx);
+  if (d.ndim == 3) {
+    L.eta_tiles = adj_tiles(d.nx, d.ny, d.nz);
+  } else {
+    const int tx = ehe_tile_width(d.ny);
+    L.eta_tiles = (int)((d.nx + tx - 1) / tx);
+  }
   L.rr_tiles = cg_tiles((long)nvox);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -58,6 +62,7 @@ static Layout make_layout(const sense_desc& d) {
   };
   L.tw_x = take(sizeof(c32) * (size_t)d.nx);
   L.tw_y = take(sizeof(c32) * (size_t)d.ny);
+  L.tw_z = take(sizeof(c32) * (size_t)d.nz);
   L.mu_y = take(sizeof(float) * (size_t)d.ny);
   L.mask_c = take((size_t)d.ny * d.nz);
   L.rows_s = take(sizeof(int32_t) * (size_t)d.ny * d.nz);
@@ -83,7 +88,8 @@ static sense_status validate_desc(const sense_desc* d) {
   for (int st : {d->maps_storage, d->kspace_storage})
     if (st < SENSE_C64 || st > SENSE_FP16X2) return fail(SENSE_ERR_INVALID, "unknown storage format");
   if (d->maps_shared != 0 && d->maps_shared != 1) return fail(SENSE_ERR_INVALID, "maps_shared must be 0 or 1");
-  if (d->ndim == 3) return fail(SENSE_ERR_UNSUPPORTED, "3D problems are not implemented yet");
+  if (d->ndim == 3 && !length_supported(d->nz))
+    return fail(SENSE_ERR_UNSUPPORTED, "nz=" + std::to_string(d->nz) + " is not a supported transform length");
   if (!length_supported(d->ny))
     return fail(SENSE_ERR_UNSUPPORTED, "ny=" + std::to_string(d->ny) + " is not a supported transform length");
   if (d->batch > 65535 || d->ncoils > 65535) return fail(SENSE_ERR_UNSUPPORTED, "batch and coils must be <= 65535");
@@ -220,7 +226,7 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
       }
       return t;
     };
-    std::vector<c32> twx = twiddles(d.nx), twy = twiddles(d.ny);
+    std::vector<c32> twx = twiddles(d.nx), twy = twiddles(d.ny), twz = twiddles(d.nz);
     const long rows_total = d.ny * d.nz;
     std::vector<uint8_t> mask((size_t)rows_total);
     std::vector<int32_t> rs, ru;
@@ -242,6 +248,7 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
     };
     up(p->L.tw_x, twx.data(), twx.size() * sizeof(c32));
     up(p->L.tw_y, twy.data(), twy.size() * sizeof(c32));
+    up(p->L.tw_z, twz.data(), twz.size() * sizeof(c32));
     up(p->L.mu_y, mu.data(), mu.size() * sizeof(float));
     up(p->L.mask_c, mask.data(), mask.size());
     up(p->L.rows_s, rs.data(), rs.size() * sizeof(int32_t));
@@ -254,7 +261,7 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
     }
     p->tb.tw_x = p->at<c32>(p->L.tw_x);
     p->tb.tw_y = p->at<c32>(p->L.tw_y);
-    p->tb.tw_z = nullptr;
+    p->tb.tw_z = p->at<c32>(p->L.tw_z);
     p->tb.mu_y = p->at<float>(p->L.mu_y);
     p->tb.mask_c = p->at<uint8_t>(p->L.mask_c);
     p->tb.rows_s = p->at<int32_t>(p->L.rows_s);
@@ -319,8 +326,12 @@ sense_status sense_apply_EHE(sense_plan p, const void* d_p, void* d_q, double la
   hipEvent_t stop;
   s = timed_ehe_begin(p, st, &stop);
   if (s != SENSE_OK) return s;
-  hipError_t e = launch_ehe(p->g, p->tb, p->maps, static_cast<const c32*>(d_p), static_cast<c32*>(d_q),
-                            (float)lambda, p->at<double>(p->L.eta_part), st);
+  hipError_t e = p->d.ndim == 3
+                     ? launch_EHE_composed(p->g, p->tb, p->maps, static_cast<const c32*>(d_p),
+                                           static_cast<c32*>(d_q), p->at<c32>(p->L.work), (float)lambda,
+                                           p->at<double>(p->L.eta_part), st)
+                     : launch_ehe(p->g, p->tb, p->maps, static_cast<const c32*>(d_p), static_cast<c32*>(d_q),
+                                  (float)lambda, p->at<double>(p->L.eta_part), st);
   if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
   return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_apply_EHE launch");
 }
@@ -354,7 +365,14 @@ sense_status sense_cg_solve(sense_plan p, const void* d_y, void* d_x, int32_t ma
     hipEvent_t stop;
     s = timed_ehe_begin(p, st, &stop);
     if (s != SENSE_OK) return s;
-    e = launch_ehe_cg(p->g, p->tb, p->maps, r, pv, q, (float)lambda, cg, st);
+    if (p->d.ndim == 3) {
+      e = launch_cg_pupdate(p->g, r, pv, cg, st);
+      if (e == hipSuccess)
+        e = launch_EHE_composed(p->g, p->tb, p->maps, pv, q, p->at<c32>(p->L.work), (float)lambda,
+                                cg.eta_part, st);
+    } else {
+      e = launch_ehe_cg(p->g, p->tb, p->maps, r, pv, q, (float)lambda, cg, st);
+    }
     if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
     if (e == hipSuccess) e = launch_cg_update(p->g, x, r, pv, q, cg, st);
   }

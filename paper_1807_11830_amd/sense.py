@@ -123,8 +123,10 @@ def from_storage(a: torch.Tensor, storage: str) -> torch.Tensor:
     return torch.view_as_complex(a.to(torch.float32).contiguous())
 
 
-def device_bytes(nx, ny, ncoils, batch, nz=1, ndim=2, maps_storage="c64", kspace_storage="c64",
+def device_bytes(nx, ny, ncoils, batch, nz=1, ndim=None, maps_storage="c64", kspace_storage="c64",
                  maps_shared=True) -> int:
+    """Device bytes of a plan (sense_plan_device_bytes); 0 if unsupported."""
+    ndim = (3 if nz > 1 else 2) if ndim is None else ndim
     d = Desc(ndim, nx, ny, nz, ncoils, batch, STORAGE[maps_storage], STORAGE[kspace_storage],
              int(maps_shared))
     return int(lib().sense_plan_device_bytes(ctypes.byref(d)))
@@ -149,33 +151,40 @@ class Plan:
     """
 
     def __init__(self, maps: torch.Tensor, mask, batch: int = 1, maps_storage: str = "c64",
-                 kspace_storage: str = "c64", stream=None):
+                 kspace_storage: str = "c64", ndim: int | None = None, stream=None):
         if not maps.is_cuda:
             raise SenseError(1, "maps must be a GPU tensor")
-        if maps.dim() == 3:
+        m = np.asarray(mask if not torch.is_tensor(mask) else mask.cpu().numpy())
+        if ndim is None:
+            ndim = 3 if m.ndim == 2 else 2
+        if ndim not in (2, 3):
+            raise SenseError(1, "ndim must be 2 or 3")
+        packed = maps.dtype in (torch.bfloat16, torch.float16)
+        mdim = maps.dim() - (1 if packed else 0)  # 16-bit pairs carry a trailing 2
+        if mdim == ndim + 1:
             shared = True
-            ncoils, ny, nx = maps.shape
-        elif maps.dim() == 4:
+            dims = tuple(maps.shape[:mdim])
+        elif mdim == ndim + 2:
             shared = False
             if maps.shape[0] != batch:
                 raise SenseError(1, "maps batch dimension must equal batch")
-            _, ncoils, ny, nx = maps.shape
+            dims = tuple(maps.shape[1:mdim])
         else:
-            raise SenseError(1, "maps must be [C][Ny][Nx] or [B][C][Ny][Nx]")
-        self.nx, self.ny, self.ncoils, self.batch = int(nx), int(ny), int(ncoils), int(batch)
+            raise SenseError(1, f"maps must be [C]{'[Nz]' if ndim == 3 else ''}[Ny][Nx] or [B][C]...")
+        ncoils = dims[0]
+        nz, ny, nx = (1,) + dims[1:] if ndim == 2 else dims[1:]
+        self.ndim = ndim
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.ncoils, self.batch = int(ncoils), int(batch)
         self.maps_storage, self.kspace_storage = maps_storage, kspace_storage
         self.maps_shared = shared
         self.device = maps.device
-        if maps.dtype in (torch.bfloat16, torch.float16):
-            self._maps = maps.contiguous()
-        else:
-            self._maps = to_storage(maps, maps_storage)
-        m = np.ascontiguousarray(np.asarray(mask if not torch.is_tensor(mask) else mask.cpu().numpy()),
-                                 dtype=np.uint8)
-        if m.size != self.ny:
-            raise SenseError(1, f"mask needs {self.ny} entries")
+        self._maps = maps.contiguous() if packed else to_storage(maps, maps_storage)
+        m = np.ascontiguousarray(m, dtype=np.uint8)
+        if m.size != self.ny * self.nz:
+            raise SenseError(1, f"mask needs {self.ny * self.nz} entries")
         self.mask = m
-        self.desc = Desc(2, self.nx, self.ny, 1, self.ncoils, self.batch, STORAGE[maps_storage],
+        self.desc = Desc(ndim, self.nx, self.ny, self.nz, self.ncoils, self.batch, STORAGE[maps_storage],
                          STORAGE[kspace_storage], int(shared))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
@@ -205,26 +214,34 @@ class Plan:
 
     # -- shapes ------------------------------------------------------------
     @property
+    def grid(self):
+        return (self.ny, self.nx) if self.ndim == 2 else (self.nz, self.ny, self.nx)
+
+    @property
     def image_shape(self):
-        return (self.batch, self.ny, self.nx)
+        return (self.batch,) + self.grid
 
     @property
     def kspace_shape(self):
-        return (self.batch, self.ncoils, self.ny, self.nx)
+        return (self.batch, self.ncoils) + self.grid
+
+    @property
+    def nvox(self):
+        return self.nx * self.ny * self.nz
 
     def _img(self, t: torch.Tensor, name: str):
         if t.dtype != torch.complex64 or not t.is_contiguous() or t.device != self.device:
             raise SenseError(1, f"{name} must be a contiguous complex64 tensor on {self.device}")
-        if t.numel() != self.batch * self.ny * self.nx:
+        if t.numel() != self.batch * self.nvox:
             raise SenseError(1, f"{name} must have {self.image_shape} elements")
         return t
 
     def _ksp(self, t: torch.Tensor, name: str):
         if self.kspace_storage == "c64":
-            ok = t.dtype == torch.complex64 and t.numel() == self.batch * self.ncoils * self.ny * self.nx
+            ok = t.dtype == torch.complex64 and t.numel() == self.batch * self.ncoils * self.nvox
         else:
             dt = torch.bfloat16 if self.kspace_storage == "bf16" else torch.float16
-            ok = t.dtype == dt and t.numel() == 2 * self.batch * self.ncoils * self.ny * self.nx
+            ok = t.dtype == dt and t.numel() == 2 * self.batch * self.ncoils * self.nvox
         if not ok or not t.is_contiguous() or t.device != self.device:
             raise SenseError(1, f"{name} must be contiguous k-space in {self.kspace_storage} storage")
         return t
