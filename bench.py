@@ -70,6 +70,9 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--maps-storage", default="c64", choices=["c64", "bf16", "fp16"])
+    ap.add_argument("--workload", default="cgsense", choices=["cgsense", "serving", "precision", "autograd3d"],
+                    help="cgsense (default, the metric's workload); the others print their own line")
+    ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a 1 GiB device-to-device copy (reference for HBM counters)")
     return ap.parse_args()
@@ -126,7 +129,162 @@ def main():
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(slices are independent: shard the batch across processes instead)", file=sys.stderr)
         sys.exit(2)
+    {"cgsense": run_cgsense, "serving": run_serving, "precision": run_precision,
+     "autograd3d": run_autograd3d}[args.workload](args)
 
+
+def run_serving(args):
+    """512 requests (sizes 128-320, 8-32 coils, R 2-4, 25 iterations) with
+    Poisson arrivals at 0.5/0.9/1.5 x the one-at-a-time solve rate: p50/p99
+    latency and solves/s of the batching engine vs one solve at a time."""
+    import torch
+
+    from paper_1807_11830_amd.serving import (EngineExecutor, InputBank, Scheduler, SerialExecutor,
+                                              make_requests)
+
+    bank = InputBank()
+    log("serving: preparing inputs")
+    probe = make_requests(96, rate=1e9)
+    bank.prepare(probe)
+    bank.prepare(make_requests(args.requests, rate=1.0))
+    # warm up plans/graphs, then measure the one-at-a-time rate
+    ser = SerialExecutor(bank)
+    Scheduler(ser).run(make_requests(48, rate=1e9, seed=99))
+    st0 = Scheduler(ser).run(probe)
+    mu = st0.throughput
+    log(f"serving: one-at-a-time {mu:.1f} solves/s")
+    budgets = {"hbm": 200 << 30, "cap256MB": 256 << 20}
+    runs = []
+    for f in (0.5, 0.9, 1.5):
+        reqs = make_requests(args.requests, rate=f * mu)
+        for bname, budget in budgets.items():
+            ex = EngineExecutor(bank, budget, max_slots=128)
+            Scheduler(ex).run(make_requests(32, rate=1e9, seed=98))  # warm the plan pool
+            stats = Scheduler(ex).run(reqs)
+            ex.close()
+            runs.append(dict(rate_factor=f, executor="engine", budget=bname, p50_ms=stats.p50 * 1e3,
+                             p99_ms=stats.p99 * 1e3, solves_per_s=stats.throughput,
+                             max_inflight=stats.max_inflight, steps=stats.steps))
+            log(f"serving: x{f} engine[{bname}] p50 {stats.p50*1e3:.2f} ms p99 {stats.p99*1e3:.2f} ms "
+                f"{stats.throughput:.1f}/s inflight<={stats.max_inflight}")
+        reqs = make_requests(args.requests, rate=f * mu)
+        stats = Scheduler(ser).run(reqs)
+        runs.append(dict(rate_factor=f, executor="one-at-a-time", p50_ms=stats.p50 * 1e3,
+                         p99_ms=stats.p99 * 1e3, solves_per_s=stats.throughput))
+        log(f"serving: x{f} serial p50 {stats.p50*1e3:.2f} ms p99 {stats.p99*1e3:.2f} ms {stats.throughput:.1f}/s")
+    ser.close()
+    key = [r for r in runs if r["rate_factor"] == 0.9 and r.get("budget") == "hbm"][0]
+    print(json.dumps({"metric": "served recon p99 latency (Poisson arrivals at 0.9 x one-at-a-time rate)",
+                      "value": key["p99_ms"], "unit": "ms", "n_gpus": 1, "higher_is_better": False,
+                      "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "serving_512req_n128-320_c8-32_r2-4_k25",
+                                 "requests": args.requests, "one_at_a_time_solves_per_s": mu},
+                      "runs": runs}), flush=True)
+
+
+def run_precision(args):
+    """384x384, 32 coils, 8 slices, VD R=4, 40 iterations: maps and k-space
+    in c64 / bf16 / fp16 storage (fp32 arithmetic, fp64 reductions); solves/s
+    and relative L2 error against the FP64 oracle (raw and quantised inputs)
+    and against the GPU fp32 result, on slice 0."""
+    import torch
+
+    import oracle
+    from paper_1807_11830_amd import sense, synth
+
+    w = synth.PREC_384
+    B, K, n, C = w.batch, w.iters, w.n, w.ncoils
+    dev = torch.device("cuda:0")
+    imgs, maps, mask = synth.slice_inputs(w, B, per_slice_maps=True)
+    maps_t = torch.from_numpy(maps.astype(np.complex64)).to(dev)
+    imgs_t = torch.from_numpy(imgs.astype(np.complex64)).to(dev)
+    with sense.Plan(maps_t, mask, batch=B) as p0:
+        y = p0.E(imgs_t)
+    noise = synth.complex_noise((B, C, n, n)).astype(np.complex64) * mask[None, None, :, None]
+    y += torch.from_numpy(noise).to(dev)
+    out = {}
+    xs = {}
+    for st in ("c64", "bf16", "fp16"):
+        with sense.Plan(maps_t, mask, batch=B, maps_storage=st, kspace_storage=st) as plan:
+            ys = sense.to_storage(y, st)
+            plan.cg(ys, K)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                plan.cg(ys, K, sync=False)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            res = plan.cg(ys, K)
+            xs[st] = res.x[0].cpu().numpy().astype(np.complex128)
+            out[st] = {"solve_ms": dt * 1e3, "applies_per_s": B * K / dt}
+        log(f"precision: {st} {dt*1e3:.2f} ms/solve")
+    # accuracy on slice 0 against the FP64 oracle
+    y0 = y[0:1].cpu().numpy().astype(np.complex128)
+    m0 = maps[0].astype(np.complex64).astype(np.complex128)
+    t0 = time.perf_counter()
+    xo, _, _, _ = oracle.cg(y0, m0, mask, K)
+    log(f"precision: oracle slice 0 in {time.perf_counter() - t0:.1f} s")
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))  # noqa: E731
+    for st in ("c64", "bf16", "fp16"):
+        out[st]["rel_l2_vs_oracle"] = rel(xs[st], xo[0])
+        out[st]["rel_l2_vs_gpu_fp32"] = rel(xs[st], xs["c64"])
+        if st != "c64":
+            dt16 = torch.bfloat16 if st == "bf16" else torch.float16
+            q = lambda a: torch.view_as_complex(  # noqa: E731
+                torch.view_as_real(torch.from_numpy(a.astype(np.complex64))).to(dt16).float().contiguous()
+            ).numpy().astype(np.complex128)
+            xq, _, _, _ = oracle.cg(q(y0), q(m0), mask, K)
+            out[st]["rel_l2_vs_oracle_on_quantised_inputs"] = rel(xs[st], xq[0])
+        log(f"precision: {st} {out[st]}")
+    print(json.dumps({"metric": "E^H E applies/s and rel-L2 vs FP64 oracle by storage precision",
+                      "value": out["bf16"]["applies_per_s"], "unit": "applies/s", "n_gpus": 1,
+                      "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": w.name, "slices": B, "iters": K}, "variants": out}), flush=True)
+
+
+def run_autograd3d(args):
+    """256x256x128 volume, 16 coils, (ky, kz) mask R=6 with a 32x32 centre:
+    forward E plus backward E^H through torch.autograd, per second."""
+    import torch
+
+    from paper_1807_11830_amd import sense, synth
+    from paper_1807_11830_amd.autograd import sense_E
+
+    nx, ny, nz, C = 256, 256, 128, 16
+    dev = torch.device("cuda:0")
+    log("autograd3d: inputs")
+    mask = synth.mask_variable_density_2d(ny, nz, 6.0, (32, 32))
+    maps = torch.from_numpy(synth.coil_maps3d(nx, ny, nz, C).astype(np.complex64)).to(dev)
+    x_true = torch.from_numpy(synth.phantom3d(nx, ny, nz).astype(np.complex64)[None]).to(dev)
+    with sense.Plan(maps, mask) as plan:
+        y = plan.E(x_true)
+        x = torch.zeros_like(x_true, requires_grad=True)
+
+        def fwd_bwd():
+            r = sense_E(x, plan) - y
+            loss = (r.real ** 2 + r.imag ** 2).sum()
+            loss.backward()
+            x.grad = None
+
+        for _ in range(2):
+            fwd_bwd()
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fwd_bwd()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+    nvox = nx * ny * nz
+    print(json.dumps({"metric": "forward+backward of E per second (3D, autograd)", "value": 1.0 / dt,
+                      "unit": "fwd+bwd/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
+                      "data": "synthetic", "ms_per_step": dt * 1e3,
+                      "config": {"workload": "autograd3d_256x256x128_c16_r6", "coils": C},
+                      "algorithmic_bytes": 8 * nvox * (2 * C + 1) * 2}), flush=True)
+
+
+def run_cgsense(args):
     import torch
 
     from paper_1807_11830_amd import sense, synth

@@ -126,6 +126,14 @@ SENSE_API size_t sense_plan_device_bytes(const sense_desc* desc);
 SENSE_API sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const uint8_t* h_mask,
                                void* stream, sense_plan* out);
 
+/*
+ * Rebind the plan to another sensitivity-map buffer of the same layout and
+ * storage (for pooled plans in a server: sizes and mask stay, maps change).
+ * Drops the captured solve graph.  Not allowed while the plan is in an
+ * engine slot.
+ */
+SENSE_API sense_status sense_plan_set_maps(sense_plan plan, const void* d_maps);
+
 /* Release a plan and its device memory (synchronises the device first). */
 SENSE_API sense_status sense_plan_destroy(sense_plan plan);
 
@@ -171,6 +179,17 @@ SENSE_API sense_status sense_cg_solve(sense_plan plan, const void* d_y, void* d_
                             double rel_tol, double lambda, sense_cg_info* d_info,
                             double* d_rho_hist, void* stream);
 
+/*
+ * Graph replay of whole solves (default on).  The first sense_cg_solve with a
+ * given argument set (d_y, d_x, max_iter, rel_tol, lambda, d_info,
+ * d_rho_hist) captures every kernel of the solve into a HIP graph on a
+ * private stream; later calls with the same arguments replay it on the
+ * caller's stream with one launch.  Different arguments re-capture.  While
+ * profiling is enabled solves run eagerly.  The maps and mask never change
+ * for a plan, so a replay computes exactly what the eager launches do.
+ */
+SENSE_API sense_status sense_plan_set_graphs(sense_plan plan, int32_t enable);
+
 /* Copy the last sense_cg_solve result of every batch element to host memory
  * h_info[B]; synchronises the stream. */
 SENSE_API sense_status sense_plan_cg_info(sense_plan plan, sense_cg_info* h_info, void* stream);
@@ -183,6 +202,39 @@ SENSE_API sense_status sense_plan_cg_info(sense_plan plan, sense_cg_info* h_info
  */
 SENSE_API sense_status sense_plan_set_profiling(sense_plan plan, int32_t enable);
 SENSE_API sense_status sense_plan_profile(sense_plan plan, int64_t* n_launches, double* total_ms);
+
+/*
+ * Serving engine: continuous batching of independent single-slice solves.
+ *
+ * A slot table holds the solves in flight.  Each request brings its own plan
+ * (ndim 2, batch 1; maps, mask and sizes may differ between requests), its
+ * k-space d_y and output image d_x.  Admission needs a free slot and
+ * footprint_bytes (what the caller counts for this request: plan plus its
+ * buffers) within the remaining budget; otherwise it returns
+ * SENSE_ERR_STATE and the caller retries after poll has freed slots.  A step
+ * advances every running slot by one CG iteration with one batched launch of
+ * the fused normal operator and one batched update per distinct (ny, maps
+ * storage) group; each problem uses its own CG state and reduction order, so
+ * its result is bitwise the same as sense_cg_solve alone.  Requests admitted
+ * between steps join at the next step.  poll returns the slots whose solves
+ * are complete (d_x written; sense_plan_cg_info gives the info) and frees
+ * them.  The engine owns one stream; a plan in a slot must not be used or
+ * destroyed until its slot is polled.  All calls come from one host thread.
+ */
+typedef struct sense_engine_s* sense_engine;
+
+SENSE_API sense_status sense_engine_create(size_t budget_bytes, int32_t max_slots, sense_engine* out);
+SENSE_API sense_status sense_engine_destroy(sense_engine engine);
+SENSE_API sense_status sense_engine_admit(sense_engine engine, sense_plan plan, const void* d_y, void* d_x,
+                                          int32_t max_iter, double rel_tol, double lambda,
+                                          size_t footprint_bytes, int32_t* slot);
+SENSE_API sense_status sense_engine_step(sense_engine engine, int32_t* n_running);
+SENSE_API sense_status sense_engine_poll(sense_engine engine, int32_t* done_slots, int32_t max_done,
+                                         int32_t* n_done);
+SENSE_API sense_status sense_engine_stats(sense_engine engine, size_t* used_bytes, size_t* budget_bytes,
+                                          int32_t* active, int64_t* steps);
+/* Wait for everything the engine has enqueued. */
+SENSE_API sense_status sense_engine_sync(sense_engine engine);
 
 /* Message of the last failed call on this thread ("" if none). */
 SENSE_API const char* sense_last_error(void);

@@ -1,0 +1,264 @@
+// Continuous-batching CG-SENSE engine.
+//
+// A slot table holds the solves in flight.  Each admitted request is one
+// single-slice problem with its own plan (maps, mask, workspace, CG state),
+// k-space and output image; admission checks a free slot and a device-memory
+// budget.  A step advances every running slot by one CG iteration with one
+// batched launch of the fused normal operator and one batched update launch
+// per distinct (ny, maps storage) group: block row i of a batched launch
+// runs problem i of the group's device table, so a problem computes exactly
+// what its own launches would (results are bitwise the same alone or in any
+// mix).  Requests admitted between steps start on the next step; finished
+// slots are reported by poll and freed.  Everything is enqueued on the
+// engine's stream; the host never waits for the device except in poll's
+// event queries and the reuse of a table staging buffer.
+#include <algorithm>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "plan_internal.hpp"
+
+using namespace sense;
+
+namespace {
+
+struct Slot {
+  bool used = false;
+  bool finishing = false;
+  sense_plan plan = nullptr;
+  const void* y = nullptr;
+  c32* x = nullptr;
+  int K = 0;
+  int k = 0;
+  double tol = 0.0;
+  float lambda = 0.f;
+  size_t footprint = 0;
+  hipEvent_t done = nullptr;
+};
+
+}  // namespace
+
+struct sense_engine_s {
+  int device = -1;
+  hipStream_t st = nullptr;
+  size_t budget = 0;
+  size_t used = 0;
+  std::vector<Slot> slots;
+  // batched-launch tables: device copies and two pinned staging buffers
+  EheParams* d_ehe = nullptr;
+  UpdParams* d_upd = nullptr;
+  EheParams* h_ehe[2] = {nullptr, nullptr};
+  UpdParams* h_upd[2] = {nullptr, nullptr};
+  hipEvent_t staged[2] = {nullptr, nullptr};
+  int buf = 0;
+  long steps = 0;
+};
+
+static void engine_free(sense_engine e) {
+  if (!e) return;
+  if (e->st) (void)hipStreamSynchronize(e->st);
+  for (auto& s : e->slots)
+    if (s.done) (void)hipEventDestroy(s.done);
+  for (int i = 0; i < 2; ++i) {
+    if (e->h_ehe[i]) (void)hipHostFree(e->h_ehe[i]);
+    if (e->h_upd[i]) (void)hipHostFree(e->h_upd[i]);
+    if (e->staged[i]) (void)hipEventDestroy(e->staged[i]);
+  }
+  if (e->d_ehe) (void)hipFree(e->d_ehe);
+  if (e->d_upd) (void)hipFree(e->d_upd);
+  if (e->st) (void)hipStreamDestroy(e->st);
+  delete e;
+}
+
+extern "C" {
+
+sense_status sense_engine_create(size_t budget_bytes, int32_t max_slots, sense_engine* out) {
+  if (!out) return fail(SENSE_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 65535) return fail(SENSE_ERR_INVALID, "max_slots must be in [1, 65535]");
+  auto* e = new (std::nothrow) sense_engine_s();
+  if (!e) return fail(SENSE_ERR_NOMEM, "host allocation failed");
+  e->budget = budget_bytes;
+  e->slots.resize((size_t)max_slots);
+  hipError_t err = hipGetDevice(&e->device);
+  if (err == hipSuccess) err = hipStreamCreateWithFlags(&e->st, hipStreamNonBlocking);
+  if (err == hipSuccess) err = hipMalloc(reinterpret_cast<void**>(&e->d_ehe), sizeof(EheParams) * max_slots);
+  if (err == hipSuccess) err = hipMalloc(reinterpret_cast<void**>(&e->d_upd), sizeof(UpdParams) * max_slots);
+  for (int i = 0; i < 2 && err == hipSuccess; ++i) {
+    err = hipHostMalloc(reinterpret_cast<void**>(&e->h_ehe[i]), sizeof(EheParams) * max_slots, hipHostMallocDefault);
+    if (err == hipSuccess)
+      err = hipHostMalloc(reinterpret_cast<void**>(&e->h_upd[i]), sizeof(UpdParams) * max_slots, hipHostMallocDefault);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&e->staged[i], hipEventDisableTiming);
+  }
+  for (auto& s : e->slots)
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+  if (err != hipSuccess) {
+    engine_free(e);
+    return device_fail(err, "sense_engine_create");
+  }
+  *out = e;
+  return SENSE_OK;
+}
+
+sense_status sense_engine_destroy(sense_engine e) {
+  if (!e) return fail(SENSE_ERR_INVALID, "engine is NULL");
+  for (auto& s : e->slots)
+    if (s.used && s.plan) s.plan->busy = false;
+  engine_free(e);
+  return SENSE_OK;
+}
+
+sense_status sense_engine_admit(sense_engine e, sense_plan plan, const void* d_y, void* d_x, int32_t max_iter,
+                                double rel_tol, double lambda, size_t footprint_bytes, int32_t* slot) {
+  if (!e) return fail(SENSE_ERR_INVALID, "engine is NULL");
+  if (!slot) return fail(SENSE_ERR_INVALID, "slot is NULL");
+  *slot = -1;
+  sense_status s = check_plan(plan);
+  if (s != SENSE_OK) return s;
+  if (plan->device != e->device) return fail(SENSE_ERR_STATE, "plan and engine are on different devices");
+  if (plan->d.ndim != 2 || plan->d.batch != 1)
+    return fail(SENSE_ERR_UNSUPPORTED, "the engine serves single 2D slices (ndim 2, batch 1)");
+  if (plan->busy) return fail(SENSE_ERR_STATE, "plan is already in a slot");
+  s = check_solve_args(plan, d_y, d_x, max_iter, rel_tol, lambda);
+  if (s != SENSE_OK) return s;
+  int free_slot = -1;
+  for (size_t i = 0; i < e->slots.size(); ++i)
+    if (!e->slots[i].used) {
+      free_slot = (int)i;
+      break;
+    }
+  if (free_slot < 0) return fail(SENSE_ERR_STATE, "no free slot");
+  if (footprint_bytes > e->budget || e->used > e->budget - footprint_bytes)
+    return fail(SENSE_ERR_STATE, "device-memory budget exceeded");
+
+  Slot& sl = e->slots[(size_t)free_slot];
+  const CgArgs cg = plan->cg_args(rel_tol, nullptr, 0);
+  hipError_t err = enqueue_solve_begin(plan, d_y, static_cast<c32*>(d_x), cg, e->st);
+  if (err == hipSuccess && max_iter == 0) {
+    err = enqueue_solve_end(plan, cg, nullptr, e->st);
+    if (err == hipSuccess) err = hipEventRecord(sl.done, e->st);
+  }
+  if (err != hipSuccess) return device_fail(err, "sense_engine_admit");
+  sl.used = true;
+  sl.finishing = max_iter == 0;
+  sl.plan = plan;
+  sl.y = d_y;
+  sl.x = static_cast<c32*>(d_x);
+  sl.K = max_iter;
+  sl.k = 0;
+  sl.tol = rel_tol;
+  sl.lambda = (float)lambda;
+  sl.footprint = footprint_bytes;
+  plan->busy = true;
+  e->used += footprint_bytes;
+  *slot = free_slot;
+  return SENSE_OK;
+}
+
+sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
+  if (!e) return fail(SENSE_ERR_INVALID, "engine is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != e->device)
+    return fail(SENSE_ERR_STATE, "current HIP device differs from the engine's device");
+  // group the running slots by (ny, maps storage): one batched launch each
+  std::map<std::pair<long, int>, std::vector<int>> groups;
+  for (size_t i = 0; i < e->slots.size(); ++i) {
+    const Slot& sl = e->slots[i];
+    if (sl.used && !sl.finishing) groups[{sl.plan->d.ny, sl.plan->d.maps_storage}].push_back((int)i);
+  }
+  int running = 0;
+  for (auto& g : groups) running += (int)g.second.size();
+  if (n_running) *n_running = running;
+  if (running == 0) return SENSE_OK;
+
+  // the staging buffer used two steps ago must have been consumed
+  const int b = e->buf;
+  hipError_t err = hipEventSynchronize(e->staged[b]);
+  EheParams* he = e->h_ehe[b];
+  UpdParams* hu = e->h_upd[b];
+  int n = 0;
+  for (auto& g : groups)
+    for (int i : g.second) {
+      Slot& sl = e->slots[(size_t)i];
+      sense_plan p = sl.plan;
+      const CgArgs cg = p->cg_args(sl.tol, nullptr, 0);
+      c32* r = p->at<c32>(p->L.r);
+      c32* pv = p->at<c32>(p->L.p);
+      c32* q = p->at<c32>(p->L.q);
+      fill_ehe_cg_params(p->g, p->tb, p->maps, r, pv, q, sl.lambda, cg, &he[n]);
+      hu[n] = UpdParams{sl.x, r, pv, q, p->g.nx * p->g.ny * p->g.nz, cg};
+      ++n;
+    }
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(e->d_ehe, he, sizeof(EheParams) * n, hipMemcpyHostToDevice, e->st);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(e->d_upd, hu, sizeof(UpdParams) * n, hipMemcpyHostToDevice, e->st);
+  if (err == hipSuccess) err = hipEventRecord(e->staged[b], e->st);
+  e->buf ^= 1;
+
+  int off = 0;
+  for (auto& g : groups) {
+    const int cnt = (int)g.second.size();
+    int max_tiles = 0, max_rr = 0;
+    for (int j = 0; j < cnt; ++j) {
+      max_tiles = std::max(max_tiles, he[off + j].ntiles);
+      max_rr = std::max(max_rr, hu[off + j].cg.rr_tiles);
+    }
+    if (err == hipSuccess) err = launch_ehe_table(g.first.first, g.first.second, e->d_ehe + off, cnt, max_tiles, e->st);
+    if (err == hipSuccess) err = launch_cg_update_table(e->d_upd + off, cnt, max_rr, e->st);
+    off += cnt;
+  }
+  for (auto& g : groups)
+    for (int i : g.second) {
+      Slot& sl = e->slots[(size_t)i];
+      if (++sl.k == sl.K && err == hipSuccess) {
+        err = enqueue_solve_end(sl.plan, sl.plan->cg_args(sl.tol, nullptr, 0), nullptr, e->st);
+        if (err == hipSuccess) err = hipEventRecord(sl.done, e->st);
+        sl.finishing = true;
+      }
+    }
+  ++e->steps;
+  return err == hipSuccess ? SENSE_OK : device_fail(err, "sense_engine_step");
+}
+
+sense_status sense_engine_poll(sense_engine e, int32_t* done_slots, int32_t max_done, int32_t* n_done) {
+  if (!e) return fail(SENSE_ERR_INVALID, "engine is NULL");
+  if (!n_done || (max_done > 0 && !done_slots)) return fail(SENSE_ERR_INVALID, "outputs must be non-NULL");
+  int32_t n = 0;
+  for (size_t i = 0; i < e->slots.size() && n < max_done; ++i) {
+    Slot& sl = e->slots[i];
+    if (!sl.used || !sl.finishing) continue;
+    const hipError_t q = hipEventQuery(sl.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return device_fail(q, "sense_engine_poll");
+    sl.plan->busy = false;
+    e->used -= sl.footprint;
+    sl = Slot{false, false, nullptr, nullptr, nullptr, 0, 0, 0.0, 0.f, 0, sl.done};
+    done_slots[n++] = (int32_t)i;
+  }
+  *n_done = n;
+  return SENSE_OK;
+}
+
+sense_status sense_engine_stats(sense_engine e, size_t* used_bytes, size_t* budget_bytes, int32_t* active,
+                                int64_t* steps) {
+  if (!e) return fail(SENSE_ERR_INVALID, "engine is NULL");
+  int32_t a = 0;
+  for (auto& s : e->slots) a += s.used ? 1 : 0;
+  if (used_bytes) *used_bytes = e->used;
+  if (budget_bytes) *budget_bytes = e->budget;
+  if (active) *active = a;
+  if (steps) *steps = e->steps;
+  return SENSE_OK;
+}
+
+sense_status sense_engine_sync(sense_engine e) {
+  if (!e) return fail(SENSE_ERR_INVALID, "engine is NULL");
+  const hipError_t err = hipStreamSynchronize(e->st);
+  return err == hipSuccess ? SENSE_OK : device_fail(err, "sense_engine_sync");
+}
+
+}  // extern "C"

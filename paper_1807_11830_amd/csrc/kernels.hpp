@@ -74,6 +74,41 @@ struct CgArgs {
   double tol;
 };
 
+// Arguments of the fused 2D normal-operator kernel (one launch, or one row
+// of a batched table launch).
+struct EheParams {
+  const void* maps;
+  const c32* r;      // CG: residual (p = r + beta p_old); apply: unused
+  const c32* p_in;   // apply: p; CG: p_old
+  c32* p_out;        // CG: new p (same buffer as p_in)
+  c32* q;
+  const c32* tw;     // [ny]
+  const float* mu;   // [ny]
+  double* eta_part;  // [B][ntiles] or null
+  int ntiles;        // column tiles of one batch element
+  long nx;
+  long maps_bstride;
+  int ncoils;
+  float lambda;
+  // CG only
+  CgState* state;
+  const double* rr_part;
+  int rr_tiles;
+  double* rho_hist;
+  int hist_len;
+  double tol;
+};
+
+// Arguments of one problem of the batched CG update.
+struct UpdParams {
+  c32* x;
+  c32* r;
+  const c32* p;
+  const c32* q;
+  long nvox;
+  CgArgs cg;
+};
+
 // Supported transform lengths (compile-time instantiations).
 bool length_supported(long n);
 // Tiles of the fused E^H E kernel along x for a given ny.
@@ -90,8 +125,15 @@ hipError_t launch_cg_init(const Geom& g, const c32* b, c32* x, c32* r, c32* p,
                           const CgArgs& cg, hipStream_t st);
 hipError_t launch_cg_update(const Geom& g, c32* x, c32* r, const c32* p, const c32* q,
                             const CgArgs& cg, hipStream_t st);
-hipError_t launch_cg_finish(const Geom& g, const CgArgs& cg, CgInfo* info, hipStream_t st);
+hipError_t launch_cg_finish(const Geom& g, const CgArgs& cg, CgInfo* info, CgInfo* info2, hipStream_t st);
 hipError_t launch_cg_pupdate(const Geom& g, const c32* r, c32* p, const CgArgs& cg, hipStream_t st);
+
+// Batched CG iteration over single-slice problems (serving engine).
+void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, const c32* r, c32* p, c32* q,
+                        float lambda, const CgArgs& cg, EheParams* out);
+hipError_t launch_ehe_table(long ny, int maps_storage, const EheParams* d_table, int nproblems, int max_tiles,
+                            hipStream_t st);
+hipError_t launch_cg_update_table(const UpdParams* d_table, int nproblems, int max_tiles, hipStream_t st);
 
 // Full-grid forward and adjoint operators (2D).
 hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32* x, c32* work,

@@ -60,12 +60,10 @@ __global__ void __launch_bounds__(CG_NT) cg_init_kernel(const c32* __restrict__ 
   }
 }
 
-__global__ void __launch_bounds__(CG_NT) cg_update_kernel(c32* __restrict__ x, c32* __restrict__ r,
-                                                          const c32* __restrict__ p,
-                                                          const c32* __restrict__ q, long nvox,
-                                                          CgArgs cg) {
+__device__ __forceinline__ void cg_update_body(c32* __restrict__ x, c32* __restrict__ r,
+                                               const c32* __restrict__ p, const c32* __restrict__ q,
+                                               long nvox, const CgArgs& cg, const int b, const int tile) {
   __shared__ double red[CG_NT / 64];
-  const int b = blockIdx.y;
   CgState* st = cg.state + b;
   if (st->status != CG_RUNNING) return;
   const double eta = ordered_sum(cg.eta_part + (long)b * cg.eta_tiles, cg.eta_tiles);
@@ -73,12 +71,12 @@ __global__ void __launch_bounds__(CG_NT) cg_update_kernel(c32* __restrict__ x, c
   if (!finite64(eta)) stop = CG_NONFINITE;
   else if (eta <= 0.0) stop = CG_BREAKDOWN;
   if (stop != CG_RUNNING) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->status = stop;
+    if (tile == 0 && threadIdx.x == 0) st->status = stop;
     return;
   }
   const double alpha = st->rho_cur / eta;
 
-  const long base = (long)b * nvox + (long)blockIdx.x * CG_CHUNK;
+  const long base = (long)b * nvox + (long)tile * CG_CHUNK;
   const long lim = (long)b * nvox + nvox;
   double acc = 0.0;
 #pragma unroll
@@ -105,12 +103,32 @@ __global__ void __launch_bounds__(CG_NT) cg_update_kernel(c32* __restrict__ x, c
   }
   const double tot = block_sum<CG_NT>(acc, red);
   if (threadIdx.x == 0) {
-    cg.rr_part[(long)b * cg.rr_tiles + blockIdx.x] = tot;
-    if (blockIdx.x == 0) st->iter = st->iter + 1;
+    cg.rr_part[(long)b * cg.rr_tiles + tile] = tot;
+    if (tile == 0) st->iter = st->iter + 1;
   }
 }
 
-__global__ void cg_finish_kernel(CgArgs cg, CgInfo* info) {
+__global__ void __launch_bounds__(CG_NT) cg_update_kernel(c32* __restrict__ x, c32* __restrict__ r,
+                                                          const c32* __restrict__ p,
+                                                          const c32* __restrict__ q, long nvox,
+                                                          CgArgs cg) {
+  cg_update_body(x, r, p, q, nvox, cg, blockIdx.y, blockIdx.x);
+}
+
+// Batched update: block row blockIdx.y updates problem table[blockIdx.y].
+__global__ void __launch_bounds__(CG_NT) cg_update_table_kernel(const UpdParams* __restrict__ table) {
+  const UpdParams U = table[blockIdx.y];
+  if ((long)blockIdx.x >= (long)U.cg.rr_tiles) return;
+  cg_update_body(U.x, U.r, U.p, U.q, U.nvox, U.cg, 0, blockIdx.x);
+}
+
+hipError_t launch_cg_update_table(const UpdParams* d_table, int nproblems, int max_tiles, hipStream_t st) {
+  hipLaunchKernelGGL(cg_update_table_kernel, dim3((unsigned)max_tiles, (unsigned)nproblems), dim3(CG_NT), 0,
+                     st, d_table);
+  return hipGetLastError();
+}
+
+__global__ void cg_finish_kernel(CgArgs cg, CgInfo* info, CgInfo* info2) {
   const int b = blockIdx.x;
   if (threadIdx.x != 0) return;
   CgState* st = cg.state + b;
@@ -131,14 +149,13 @@ __global__ void cg_finish_kernel(CgArgs cg, CgInfo* info) {
   } else {
     rho_final = st->rho[k & 1];
   }
-  if (info) {
-    CgInfo o;
-    o.iters_run = k;
-    o.status = status;
-    o.rho0 = rho0;
-    o.rho_final = rho_final;
-    info[b] = o;
-  }
+  CgInfo o;
+  o.iters_run = k;
+  o.status = status;
+  o.rho0 = rho0;
+  o.rho_final = rho_final;
+  if (info) info[b] = o;
+  if (info2) info2[b] = o;
 }
 
 // p = r + beta p with the start-of-iteration scalar logic (used where the
@@ -190,8 +207,8 @@ hipError_t launch_cg_update(const Geom& g, c32* x, c32* r, const c32* p, const c
   return hipGetLastError();
 }
 
-hipError_t launch_cg_finish(const Geom& g, const CgArgs& cg, CgInfo* info, hipStream_t st) {
-  hipLaunchKernelGGL(cg_finish_kernel, dim3((unsigned)g.batch), dim3(64), 0, st, cg, info);
+hipError_t launch_cg_finish(const Geom& g, const CgArgs& cg, CgInfo* info, CgInfo* info2, hipStream_t st) {
+  hipLaunchKernelGGL(cg_finish_kernel, dim3((unsigned)g.batch), dim3(64), 0, st, cg, info, info2);
   return hipGetLastError();
 }
 

@@ -25,31 +25,9 @@
 
 namespace sense {
 
-struct EheParams {
-  const void* maps;
-  const c32* r;      // CG: residual (p = r + beta p_old); apply: unused
-  const c32* p_in;   // apply: p; CG: p_old
-  c32* p_out;        // CG: new p (same buffer as p_in)
-  c32* q;
-  const c32* tw;     // [ny]
-  const float* mu;   // [ny]
-  double* eta_part;  // [B][gridDim.x] or null
-  long nx;
-  long maps_bstride;
-  int ncoils;
-  float lambda;
-  // CG only
-  CgState* state;
-  const double* rr_part;
-  int rr_tiles;
-  double* rho_hist;
-  int hist_len;
-  double tol;
-};
 
 template <int N, int ST, bool CG>
-__global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX)
-    ehe2d_kernel(EheParams P) {
+__device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, const int b) {
   constexpr int T = EheLen<N>::T;
   constexpr int E = EheLen<N>::E;
   constexpr int TX = EheLen<N>::TX;
@@ -69,8 +47,6 @@ __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX)
   const int tid = threadIdx.x;
   const int cx = tid % TX;
   const int t = tid / TX;
-  const int tile = blockIdx.x;
-  const int b = blockIdx.y;
   const long x = (long)tile * TX + cx;
   const bool valid = x < P.nx;
   const long nx = P.nx;
@@ -184,8 +160,25 @@ __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX)
   }
   if (P.eta_part) {
     const double tot = block_sum<NT>(eta, red);
-    if (tid == 0) P.eta_part[(long)b * gridDim.x + tile] = tot;
+    if (tid == 0) P.eta_part[(long)b * P.ntiles + tile] = tot;
   }
+}
+
+template <int N, int ST, bool CG>
+__global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX) ehe2d_kernel(EheParams P) {
+  ehe2d_body<N, ST, CG>(P, blockIdx.x, blockIdx.y);
+}
+
+// Batched CG launch over many independent single-slice problems of the same
+// ny: block row blockIdx.y runs the problem described by table[blockIdx.y]
+// (its own maps, vectors, partials and CG state), so every problem computes
+// exactly what its own launch would.
+template <int N, int ST>
+__global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX)
+    ehe2d_table_kernel(const EheParams* __restrict__ table) {
+  const EheParams P = table[blockIdx.y];
+  if ((long)blockIdx.x >= (long)P.ntiles) return;
+  ehe2d_body<N, ST, true>(P, blockIdx.x, 0);
 }
 
 int ehe_tile_width(long ny) {
@@ -203,6 +196,7 @@ static hipError_t launch_ehe_impl(const Geom& g, const Tables& tb, EheParams P, 
   P.tw = tb.tw_y;
   P.mu = tb.mu_y;
   P.nx = g.nx;
+  P.ntiles = (int)((g.nx + ehe_tile_width(g.ny) - 1) / ehe_tile_width(g.ny));
   P.maps_bstride = g.maps_bstride;
   P.ncoils = g.ncoils;
   dispatch_length(g.ny, [&](auto nc) {
@@ -215,6 +209,49 @@ static hipError_t launch_ehe_impl(const Geom& g, const Tables& tb, EheParams P, 
       case ST_C64: hipLaunchKernelGGL((ehe2d_kernel<N, ST_C64, CG>), grid, block, 0, st, P); break;
       case ST_BF16: hipLaunchKernelGGL((ehe2d_kernel<N, ST_BF16, CG>), grid, block, 0, st, P); break;
       case ST_FP16: hipLaunchKernelGGL((ehe2d_kernel<N, ST_FP16, CG>), grid, block, 0, st, P); break;
+      default: return;
+    }
+    err = hipGetLastError();
+  });
+  return err;
+}
+
+void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, const c32* r, c32* p, c32* q,
+                        float lambda, const CgArgs& cg, EheParams* out) {
+  EheParams P{};
+  P.maps = maps;
+  P.r = r;
+  P.p_in = p;
+  P.p_out = p;
+  P.q = q;
+  P.lambda = lambda;
+  P.eta_part = cg.eta_part;
+  P.state = cg.state;
+  P.rr_part = cg.rr_part;
+  P.rr_tiles = cg.rr_tiles;
+  P.rho_hist = cg.rho_hist;
+  P.hist_len = cg.hist_len;
+  P.tol = cg.tol;
+  P.tw = tb.tw_y;
+  P.mu = tb.mu_y;
+  P.nx = g.nx;
+  P.ntiles = (int)((g.nx + ehe_tile_width(g.ny) - 1) / ehe_tile_width(g.ny));
+  P.maps_bstride = g.maps_bstride;
+  P.ncoils = g.ncoils;
+  *out = P;
+}
+
+hipError_t launch_ehe_table(long ny, int maps_storage, const EheParams* d_table, int nproblems, int max_tiles,
+                            hipStream_t st) {
+  hipError_t err = hipErrorInvalidValue;
+  dispatch_length(ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    dim3 grid((unsigned)max_tiles, (unsigned)nproblems);
+    dim3 block(EheLen<N>::T * EheLen<N>::TX);
+    switch (maps_storage) {
+      case ST_C64: hipLaunchKernelGGL((ehe2d_table_kernel<N, ST_C64>), grid, block, 0, st, d_table); break;
+      case ST_BF16: hipLaunchKernelGGL((ehe2d_table_kernel<N, ST_BF16>), grid, block, 0, st, d_table); break;
+      case ST_FP16: hipLaunchKernelGGL((ehe2d_table_kernel<N, ST_FP16>), grid, block, 0, st, d_table); break;
       default: return;
     }
     err = hipGetLastError();

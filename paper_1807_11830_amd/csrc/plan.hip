@@ -16,13 +16,14 @@
 
 #include "kernels.hpp"
 #include "lengths.hpp"
+#include "plan_internal.hpp"
 #include "sense.h"
 
 namespace sense {
 
-static thread_local std::string g_last_error;
+thread_local std::string g_last_error;
 
-static sense_status fail(sense_status s, const std::string& msg) {
+sense_status fail(sense_status s, const std::string& msg) {
   g_last_error = msg;
   return s;
 }
@@ -33,15 +34,8 @@ bool length_supported(long n) {
 
 static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-static size_t storage_bytes(int st) { return st == ST_C64 ? 8 : 4; }
+size_t storage_bytes(int st) { return st == ST_C64 ? 8 : 4; }
 
-struct Layout {
-  size_t tw_x, tw_y, tw_z, mu_y, mask_c, rows_s, rows_u;
-  size_t work, r, p, q;
-  size_t state, eta_part, rr_part, info;
-  size_t total;
-  int eta_tiles, rr_tiles;
-};
 
 static Layout make_layout(const sense_desc& d) {
   Layout L{};
@@ -105,39 +99,8 @@ static sense_status validate_desc(const sense_desc* d) {
 
 using namespace sense;
 
-struct sense_plan_s {
-  sense_desc d;
-  Geom g;
-  Layout L;
-  int device;
-  bool full_ops;  // nx is a supported transform length (E, E^H, CG)
-  const void* maps;
-  char* mem;
-  Tables tb;
-  int n_rows_s, n_rows_u;
-  bool profiling;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-  size_t events_used;
 
-  template <class T>
-  T* at(size_t off) const {
-    return reinterpret_cast<T*>(mem + off);
-  }
-  CgArgs cg_args(double tol, double* hist, int hist_len) const {
-    CgArgs a{};
-    a.state = at<CgState>(L.state);
-    a.eta_part = at<double>(L.eta_part);
-    a.rr_part = at<double>(L.rr_part);
-    a.eta_tiles = L.eta_tiles;
-    a.rr_tiles = L.rr_tiles;
-    a.rho_hist = hist;
-    a.hist_len = hist_len;
-    a.tol = tol;
-    return a;
-  }
-};
-
-static sense_status check_plan(sense_plan p) {
+sense_status check_plan(sense_plan p) {
   if (!p) return fail(SENSE_ERR_INVALID, "plan is NULL");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
@@ -145,13 +108,13 @@ static sense_status check_plan(sense_plan p) {
   return SENSE_OK;
 }
 
-static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+bool sense::overlap(const void* a, size_t na, const void* b, size_t nb) {
   const char* x = static_cast<const char*>(a);
   const char* y = static_cast<const char*>(b);
   return x < y + nb && y < x + na;
 }
 
-static sense_status device_fail(hipError_t e, const char* what) {
+sense_status sense::device_fail(hipError_t e, const char* what) {
   return fail(SENSE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
@@ -167,6 +130,63 @@ static sense_status timed_ehe_begin(sense_plan p, hipStream_t st, hipEvent_t* st
   auto& pr = p->events[p->events_used++];
   if (hipEventRecord(pr.first, st) != hipSuccess) return fail(SENSE_ERR_DEVICE, "hipEventRecord failed");
   *stop = pr.second;
+  return SENSE_OK;
+}
+
+// Solve pieces (also used by the serving engine): E^H y and CG init; one
+// iteration; the final test.  All enqueue only.
+hipError_t enqueue_solve_begin(sense_plan p, const void* d_y, c32* x, const CgArgs& cg,
+                                      hipStream_t st) {
+  c32* r = p->at<c32>(p->L.r);
+  hipError_t e = launch_EH(p->g, p->tb, p->maps, d_y, p->at<c32>(p->L.work), r, st);
+  if (e == hipSuccess) e = launch_cg_init(p->g, r, x, r, p->at<c32>(p->L.p), cg, st);
+  return e;
+}
+
+hipError_t enqueue_iteration(sense_plan p, c32* x, float lambda, const CgArgs& cg, hipStream_t st) {
+  c32* r = p->at<c32>(p->L.r);
+  c32* pv = p->at<c32>(p->L.p);
+  c32* q = p->at<c32>(p->L.q);
+  hipEvent_t stop = nullptr;
+  if (timed_ehe_begin(p, st, &stop) != SENSE_OK) return hipErrorUnknown;
+  hipError_t e;
+  if (p->d.ndim == 3) {
+    e = launch_cg_pupdate(p->g, r, pv, cg, st);
+    if (e == hipSuccess)
+      e = launch_EHE_composed(p->g, p->tb, p->maps, pv, q, p->at<c32>(p->L.work), lambda, cg.eta_part, st);
+  } else {
+    e = launch_ehe_cg(p->g, p->tb, p->maps, r, pv, q, lambda, cg, st);
+  }
+  if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
+  if (e == hipSuccess) e = launch_cg_update(p->g, x, r, pv, q, cg, st);
+  return e;
+}
+
+hipError_t enqueue_solve_end(sense_plan p, const CgArgs& cg, CgInfo* d_info, hipStream_t st) {
+  return launch_cg_finish(p->g, cg, p->at<CgInfo>(p->L.info), d_info, st);
+}
+
+static hipError_t enqueue_solve(sense_plan p, const void* d_y, c32* x, int32_t max_iter, float lambda,
+                                const CgArgs& cg, CgInfo* d_info, hipStream_t st) {
+  hipError_t e = enqueue_solve_begin(p, d_y, x, cg, st);
+  for (int k = 0; k < max_iter && e == hipSuccess; ++k) e = enqueue_iteration(p, x, lambda, cg, st);
+  if (e == hipSuccess) e = enqueue_solve_end(p, cg, d_info, st);
+  return e;
+}
+
+sense_status check_solve_args(sense_plan p, const void* d_y, void* d_x, int32_t max_iter,
+                                     double rel_tol, double lambda) {
+  if (!d_x || !d_y) return fail(SENSE_ERR_INVALID, "d_x and d_y must be non-NULL");
+  if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
+  if (max_iter < 0) return fail(SENSE_ERR_INVALID, "max_iter must be >= 0");
+  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return fail(SENSE_ERR_INVALID, "rel_tol must be finite and >= 0");
+  if (!std::isfinite(lambda)) return fail(SENSE_ERR_INVALID, "lambda must be finite");
+  const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
+  const size_t xb = nvox * p->d.batch * sizeof(c32);
+  const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
+  if (overlap(d_x, xb, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_x and d_y overlap");
+  if (overlap(d_x, xb, p->mem, p->L.total) || overlap(d_y, yb, p->mem, p->L.total))
+    return fail(SENSE_ERR_INVALID, "buffers overlap the plan workspace");
   return SENSE_OK;
 }
 
@@ -196,6 +216,10 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
     p->full_ops = length_supported(d.nx);
     p->profiling = false;
     p->events_used = 0;
+    p->graphs = true;
+    p->busy = false;
+    p->cap_stream = nullptr;
+    p->gexec = nullptr;
     if (hipGetDevice(&p->device) != hipSuccess) {
       delete p;
       return fail(SENSE_ERR_DEVICE, "hipGetDevice failed");
@@ -277,7 +301,10 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
 
 sense_status sense_plan_destroy(sense_plan p) {
   if (!p) return fail(SENSE_ERR_INVALID, "plan is NULL");
+  if (p->busy) return fail(SENSE_ERR_STATE, "plan is in a serving-engine slot");
   (void)hipDeviceSynchronize();
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (auto& pr : p->events) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
@@ -340,47 +367,64 @@ sense_status sense_cg_solve(sense_plan p, const void* d_y, void* d_x, int32_t ma
                             double lambda, sense_cg_info* d_info, double* d_rho_hist, void* stream) {
   sense_status s = check_plan(p);
   if (s != SENSE_OK) return s;
-  if (!d_x || !d_y) return fail(SENSE_ERR_INVALID, "d_x and d_y must be non-NULL");
-  if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
-  if (max_iter < 0) return fail(SENSE_ERR_INVALID, "max_iter must be >= 0");
-  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return fail(SENSE_ERR_INVALID, "rel_tol must be finite and >= 0");
-  if (!std::isfinite(lambda)) return fail(SENSE_ERR_INVALID, "lambda must be finite");
-  const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
-  const size_t xb = nvox * p->d.batch * sizeof(c32);
-  const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
-  if (overlap(d_x, xb, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_x and d_y overlap");
-  if (overlap(d_x, xb, p->mem, p->L.total) || overlap(d_y, yb, p->mem, p->L.total))
-    return fail(SENSE_ERR_INVALID, "buffers overlap the plan workspace");
-
+  s = check_solve_args(p, d_y, d_x, max_iter, rel_tol, lambda);
+  if (s != SENSE_OK) return s;
+  if (p->busy) return fail(SENSE_ERR_STATE, "plan is in a serving-engine slot");
   hipStream_t st = static_cast<hipStream_t>(stream);
   c32* x = static_cast<c32*>(d_x);
-  c32* r = p->at<c32>(p->L.r);
-  c32* pv = p->at<c32>(p->L.p);
-  c32* q = p->at<c32>(p->L.q);
+  CgInfo* info2 = reinterpret_cast<CgInfo*>(d_info);
   const CgArgs cg = p->cg_args(rel_tol, d_rho_hist, d_rho_hist ? max_iter + 1 : 0);
 
-  hipError_t e = launch_EH(p->g, p->tb, p->maps, d_y, p->at<c32>(p->L.work), r, st);
-  if (e == hipSuccess) e = launch_cg_init(p->g, r, x, r, pv, cg, st);
-  for (int k = 0; k < max_iter && e == hipSuccess; ++k) {
-    hipEvent_t stop;
-    s = timed_ehe_begin(p, st, &stop);
-    if (s != SENSE_OK) return s;
-    if (p->d.ndim == 3) {
-      e = launch_cg_pupdate(p->g, r, pv, cg, st);
-      if (e == hipSuccess)
-        e = launch_EHE_composed(p->g, p->tb, p->maps, pv, q, p->at<c32>(p->L.work), (float)lambda,
-                                cg.eta_part, st);
-    } else {
-      e = launch_ehe_cg(p->g, p->tb, p->maps, r, pv, q, (float)lambda, cg, st);
-    }
-    if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
-    if (e == hipSuccess) e = launch_cg_update(p->g, x, r, pv, q, cg, st);
+  if (!p->graphs || p->profiling) {
+    hipError_t e = enqueue_solve(p, d_y, x, max_iter, (float)lambda, cg, info2, st);
+    return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_cg_solve launch");
   }
-  CgInfo* info = p->at<CgInfo>(p->L.info);
-  if (e == hipSuccess) e = launch_cg_finish(p->g, cg, info, st);
-  if (e == hipSuccess && d_info)
-    e = hipMemcpyAsync(d_info, info, sizeof(CgInfo) * p->d.batch, hipMemcpyDeviceToDevice, st);
-  return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_cg_solve launch");
+  // Graph path: capture the whole solve once on the plan's private stream,
+  // then replay it on the caller's stream while the arguments repeat.
+  const sense_plan_s::SolveKey key{d_y, d_x, max_iter, rel_tol, lambda, d_info, d_rho_hist};
+  hipError_t e = hipSuccess;
+  if (!p->gexec || !(key == p->gkey)) {
+    if (p->gexec) {
+      (void)hipGraphExecDestroy(p->gexec);
+      p->gexec = nullptr;
+    }
+    if (!p->cap_stream) e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking);
+    hipGraph_t graph = nullptr;
+    if (e == hipSuccess) e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t e2 = enqueue_solve(p, d_y, x, max_iter, (float)lambda, cg, info2, p->cap_stream);
+      e = hipStreamEndCapture(p->cap_stream, &graph);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      p->gexec = nullptr;
+      return device_fail(e, "sense_cg_solve graph capture");
+    }
+    p->gkey = key;
+  }
+  e = hipGraphLaunch(p->gexec, st);
+  return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_cg_solve graph launch");
+}
+
+sense_status sense_plan_set_maps(sense_plan p, const void* d_maps) {
+  sense_status s = check_plan(p);
+  if (s != SENSE_OK) return s;
+  if (!d_maps) return fail(SENSE_ERR_INVALID, "d_maps is NULL");
+  if (p->busy) return fail(SENSE_ERR_STATE, "plan is in a serving-engine slot");
+  p->maps = d_maps;
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  return SENSE_OK;
+}
+
+sense_status sense_plan_set_graphs(sense_plan p, int32_t enable) {
+  if (!p) return fail(SENSE_ERR_INVALID, "plan is NULL");
+  p->graphs = enable != 0;
+  return SENSE_OK;
 }
 
 sense_status sense_plan_cg_info(sense_plan p, sense_cg_info* h_info, void* stream) {

@@ -1,0 +1,88 @@
+// Plan internals shared by the C ABI implementation (plan.hip) and the
+// serving engine (engine.hip).  Not part of the public interface.
+#pragma once
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "kernels.hpp"
+#include "sense.h"
+
+namespace sense {
+
+struct Layout {
+  size_t tw_x, tw_y, tw_z, mu_y, mask_c, rows_s, rows_u;
+  size_t work, r, p, q;
+  size_t state, eta_part, rr_part, info;
+  size_t total;
+  int eta_tiles, rr_tiles;
+};
+
+sense_status fail(sense_status s, const std::string& msg);
+sense_status device_fail(hipError_t e, const char* what);
+bool overlap(const void* a, size_t na, const void* b, size_t nb);
+size_t storage_bytes(int st);
+
+}  // namespace sense
+
+struct sense_plan_s {
+  using CgArgs = sense::CgArgs;
+  using Geom = sense::Geom;
+  using Layout = sense::Layout;
+  using Tables = sense::Tables;
+  sense_desc d;
+  Geom g;
+  Layout L;
+  int device;
+  bool full_ops;  // nx is a supported transform length (E, E^H, CG)
+  const void* maps;
+  char* mem;
+  Tables tb;
+  int n_rows_s, n_rows_u;
+  bool profiling;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used;
+  bool busy;  // owned by a serving-engine slot
+  // whole-solve graph, replayed while the solve arguments repeat
+  bool graphs;
+  hipStream_t cap_stream;
+  hipGraphExec_t gexec;
+  struct SolveKey {
+    const void* y;
+    void* x;
+    int32_t max_iter;
+    double tol, lambda;
+    void* info;
+    double* hist;
+    bool operator==(const SolveKey& o) const {
+      return y == o.y && x == o.x && max_iter == o.max_iter && tol == o.tol && lambda == o.lambda &&
+             info == o.info && hist == o.hist;
+    }
+  } gkey;
+
+  template <class T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(mem + off);
+  }
+  CgArgs cg_args(double tol, double* hist, int hist_len) const {
+    CgArgs a{};
+    a.state = at<sense::CgState>(L.state);
+    a.eta_part = at<double>(L.eta_part);
+    a.rr_part = at<double>(L.rr_part);
+    a.eta_tiles = L.eta_tiles;
+    a.rr_tiles = L.rr_tiles;
+    a.rho_hist = hist;
+    a.hist_len = hist_len;
+    a.tol = tol;
+    return a;
+  }
+};
+
+sense_status check_plan(sense_plan p);
+sense_status check_solve_args(sense_plan p, const void* d_y, void* d_x, int32_t max_iter, double rel_tol,
+                              double lambda);
+hipError_t enqueue_solve_begin(sense_plan p, const void* d_y, sense::c32* x, const sense::CgArgs& cg,
+                               hipStream_t st);
+hipError_t enqueue_iteration(sense_plan p, sense::c32* x, float lambda, const sense::CgArgs& cg, hipStream_t st);
+hipError_t enqueue_solve_end(sense_plan p, const sense::CgArgs& cg, sense::CgInfo* d_info, hipStream_t st);

@@ -54,7 +54,9 @@ class CgInfo(ctypes.Structure):
 ABI_FUNCTIONS = ("sense_plan_device_bytes", "sense_plan_create", "sense_plan_destroy",
                  "sense_apply_E", "sense_apply_EH", "sense_apply_EHE", "sense_cg_solve",
                  "sense_plan_cg_info", "sense_plan_set_profiling", "sense_plan_profile",
-                 "sense_last_error", "sense_version")
+                 "sense_plan_set_graphs", "sense_plan_set_maps", "sense_engine_create", "sense_engine_destroy",
+                 "sense_engine_admit", "sense_engine_step", "sense_engine_poll", "sense_engine_stats",
+                 "sense_engine_sync", "sense_last_error", "sense_version")
 
 _lib = None
 
@@ -79,7 +81,17 @@ def lib():
     L.sense_cg_solve.argtypes = [P, P, P, I32, D, D, P, P, P]
     L.sense_plan_cg_info.argtypes = [P, P, P]
     L.sense_plan_set_profiling.argtypes = [P, I32]
+    L.sense_plan_set_graphs.argtypes = [P, I32]
+    L.sense_plan_set_maps.argtypes = [P, P]
     L.sense_plan_profile.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(D)]
+    L.sense_engine_create.argtypes = [ctypes.c_size_t, I32, ctypes.POINTER(P)]
+    L.sense_engine_destroy.argtypes = [P]
+    L.sense_engine_admit.argtypes = [P, P, P, P, I32, D, D, ctypes.c_size_t, ctypes.POINTER(I32)]
+    L.sense_engine_step.argtypes = [P, ctypes.POINTER(I32)]
+    L.sense_engine_poll.argtypes = [P, ctypes.POINTER(I32), I32, ctypes.POINTER(I32)]
+    L.sense_engine_stats.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(I32), ctypes.POINTER(I64)]
+    L.sense_engine_sync.argtypes = [P]
     L.sense_last_error.argtypes = []
     L.sense_last_error.restype = ctypes.c_char_p
     L.sense_version.argtypes = []
@@ -297,6 +309,20 @@ class Plan:
         return CgResult(x, np.array([i.iters_run for i in info]), np.array([i.status for i in info]),
                         np.array([i.rho0 for i in info]), np.array([i.rho_final for i in info]), hist)
 
+    def set_maps(self, maps: torch.Tensor):
+        """Rebind to another map buffer of the same shape and storage."""
+        m = maps.contiguous() if maps.dtype in (torch.bfloat16, torch.float16) \
+            else to_storage(maps, self.maps_storage)
+        if m.numel() != self._maps.numel() or m.dtype != self._maps.dtype:
+            raise SenseError(1, "maps must keep the plan's shape and storage")
+        with torch.cuda.device(self.device):
+            _check(lib().sense_plan_set_maps(self._h, _ptr(m)))
+        self._maps = m
+
+    def set_graphs(self, on: bool):
+        """Replay whole solves from a captured HIP graph (default on)."""
+        _check(lib().sense_plan_set_graphs(self._h, int(bool(on))))
+
     # -- profiling -------------------------------------------------------------
     def set_profiling(self, on: bool):
         _check(lib().sense_plan_set_profiling(self._h, int(bool(on))))
@@ -308,3 +334,74 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(lib().sense_plan_profile(self._h, ctypes.byref(n), ctypes.byref(ms)))
         return int(n.value), float(ms.value)
+
+
+class Engine:
+    """Continuous-batching CG engine (sense_engine_*): a slot table of
+    single-slice solves advanced together, one CG iteration per step."""
+
+    def __init__(self, budget_bytes: int, max_slots: int, device=None):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.max_slots = int(max_slots)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().sense_engine_create(int(budget_bytes), self.max_slots, ctypes.byref(h)))
+        self._h = h
+        self._done = (ctypes.c_int32 * self.max_slots)()
+
+    def admit(self, plan: Plan, y: torch.Tensor, x: torch.Tensor, max_iter: int, tol: float = 0.0,
+              lam: float = 0.0, footprint: int = 0):
+        """Slot index, or None when no slot or budget is free right now."""
+        plan._ksp(y, "y")
+        plan._img(x, "x")
+        slot = ctypes.c_int32(-1)
+        with torch.cuda.device(self.device):
+            rc = lib().sense_engine_admit(self._h, plan._h, _ptr(y), _ptr(x), int(max_iter), float(tol),
+                                          float(lam), int(footprint), ctypes.byref(slot))
+        if rc == 5:  # SENSE_ERR_STATE: full or over budget -> try again later
+            msg = lib().sense_last_error().decode()
+            if "no free slot" in msg or "budget" in msg:
+                return None
+        _check(rc)
+        return int(slot.value)
+
+    def step(self) -> int:
+        n = ctypes.c_int32(0)
+        with torch.cuda.device(self.device):
+            _check(lib().sense_engine_step(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def poll(self):
+        n = ctypes.c_int32(0)
+        with torch.cuda.device(self.device):
+            _check(lib().sense_engine_poll(self._h, self._done, self.max_slots, ctypes.byref(n)))
+        return [int(self._done[i]) for i in range(n.value)]
+
+    def stats(self):
+        used, budget = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        active, steps = ctypes.c_int32(0), ctypes.c_int64(0)
+        _check(lib().sense_engine_stats(self._h, ctypes.byref(used), ctypes.byref(budget),
+                                        ctypes.byref(active), ctypes.byref(steps)))
+        return dict(used=used.value, budget=budget.value, active=active.value, steps=steps.value)
+
+    def sync(self):
+        with torch.cuda.device(self.device):
+            _check(lib().sense_engine_sync(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            with torch.cuda.device(self.device):
+                _check(lib().sense_engine_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -151,3 +151,31 @@ def test_cg_full_size_batch_sampled():
         err = rel_l2(xg[b:b + 1], xo)
         log(f"slice {b}: CG rel-L2 {err:.3e}")
         assert err <= 1e-4
+
+
+def test_cg_graph_replay_matches_eager():
+    """Whole-solve graph replays, interleaved with eager work and
+    synchronisations, reproduce the eager solve bitwise every time; changed
+    arguments re-capture."""
+    w = synth.SMALL_64
+    imgs, maps, mask, y = _problem(w, batch=2, per_slice_maps=True)
+    with sense.Plan(to_dev(maps), mask, batch=2) as plan:
+        yd = to_dev(y)
+        plan.set_graphs(False)
+        ref = plan.cg(yd, 15).x.clone()
+        ref_tol = plan.cg(yd, 15, tol=1e-3).x.clone()
+        plan.set_graphs(True)
+        out = torch.empty_like(ref)
+        p = to_dev(imgs)
+        for rep in range(4):
+            res = plan.cg(yd, 15, out=out)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), rep
+            assert list(res.iters) == [15, 15]
+            plan.EHE(p)  # eager work between replays
+            (p * 2.0).sum().item()
+            torch.cuda.synchronize()
+        res = plan.cg(yd, 15, tol=1e-3, out=out)
+        assert torch.equal(out, ref_tol)
+        res = plan.cg(yd, 15, out=out)
+        assert torch.equal(out, ref)

@@ -1,0 +1,86 @@
+"""Serving engine on the GPU: each request's result is bitwise the same
+solved alone (Plan.cg) and in a continuously batched mix of sizes, coil
+counts and accelerations; budget and slot admission; plans in a slot are
+locked; one mixed request against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import TOL_FP32, log, rel_l2, to_host
+from paper_1807_11830_amd import sense
+from paper_1807_11830_amd.serving import (EngineExecutor, InputBank, Request, Scheduler, SerialExecutor,
+                                          make_requests)
+
+pytestmark = pytest.mark.gpu
+
+CLASSES = [(128, 8, 2), (192, 16, 3), (256, 8, 4), (128, 8, 2), (320, 16, 2), (192, 32, 4), (256, 16, 3)]
+
+
+def _alone(bank, r):
+    with sense.Plan(bank.coil_maps(r.n, r.ncoils), bank.mask(r.n, r.accel)) as p:
+        res = p.cg(bank.kspace(r.n, r.ncoils, r.accel), r.iters)
+        return res.x.clone(), res.iters[0], res.status[0]
+
+
+def test_alone_equals_mixed_bitwise():
+    bank = InputBank()
+    reqs = [Request(i, 0.0005 * i, n, c, a, 12) for i, (n, c, a) in enumerate(CLASSES)]
+    bank.prepare(reqs)
+    alone = {r.id: _alone(bank, r) for r in reqs}
+    ex = EngineExecutor(bank, budget_bytes=8 << 30, max_slots=8)
+    st = Scheduler(ex).run(reqs)
+    ex.close()
+    log(f"mixed run: max in flight {st.max_inflight}, steps {st.steps}")
+    assert st.max_inflight >= 2
+    for r in reqs:
+        assert torch.equal(r.result, alone[r.id][0]), r
+    # serial executor (plain path) gives the same results too
+    reqs2 = [Request(i, 0.0, n, c, a, 12) for i, (n, c, a) in enumerate(CLASSES)]
+    ex2 = SerialExecutor(bank)
+    Scheduler(ex2).run(reqs2)
+    ex2.close()
+    for r in reqs2:
+        assert torch.equal(r.result, alone[r.id][0])
+
+
+def test_mixed_request_matches_oracle():
+    bank = InputBank()
+    reqs = make_requests(10, rate=5000.0, iters=10, sizes=(128, 192), coils=(8,), accels=(2, 3))
+    bank.prepare(reqs)
+    ex = EngineExecutor(bank, budget_bytes=4 << 30, max_slots=6)
+    Scheduler(ex).run(reqs)
+    ex.close()
+    r = reqs[-1]
+    maps = bank.coil_maps(r.n, r.ncoils).cpu().numpy().astype(np.complex128)
+    y = to_host(bank.kspace(r.n, r.ncoils, r.accel))
+    xo, _, _, _ = oracle.cg(y, maps, bank.mask(r.n, r.accel), r.iters)
+    err = rel_l2(to_host(r.result), xo)
+    log(f"request {r.id} ({r.n}, {r.ncoils}, R{r.accel}) vs oracle {err:.3e}")
+    assert err <= TOL_FP32
+
+
+def test_engine_admission_limits():
+    bank = InputBank()
+    r = Request(0, 0.0, 128, 8, 2, 5)
+    bank.prepare([r])
+    maps, mask, y = bank.coil_maps(128, 8), bank.mask(128, 2), bank.kspace(128, 8, 2)
+    with sense.Engine(budget_bytes=1000, max_slots=2) as eng, sense.Plan(maps, mask) as p1, \
+            sense.Plan(maps, mask) as p2, sense.Plan(maps, mask) as p3:
+        x1, x2, x3 = (torch.empty((1, 128, 128), dtype=torch.complex64, device="cuda:0") for _ in range(3))
+        assert eng.admit(p1, y, x1, 5, footprint=2000) is None  # over budget
+        assert eng.admit(p1, y, x1, 5, footprint=400) == 0
+        with pytest.raises(sense.SenseError, match="slot"):
+            eng.admit(p1, y, x2, 5, footprint=1)  # plan already in a slot
+        with pytest.raises(sense.SenseError, match="slot"):
+            p1.cg(y, 5)
+        assert eng.admit(p2, y, x2, 5, footprint=400) == 1
+        assert eng.admit(p3, y, x3, 5, footprint=100) is None  # no free slot
+        done = []
+        while len(done) < 2:
+            eng.step()
+            done += eng.poll()
+        assert sorted(done) == [0, 1]
+        assert eng.stats()["used"] == 0
+        ref = p3.cg(y, 5).x
+        assert torch.equal(x1, ref) and torch.equal(x2, ref)
