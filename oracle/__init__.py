@@ -73,7 +73,7 @@ def _load():
         lib.or_E.argtypes = dims + [P, P, P, P]
         lib.or_EH.argtypes = dims + [P, P, P, P]
         lib.or_A.argtypes = dims + [P, P, P, D, P]
-        lib.or_cg.argtypes = dims + [P, P, P, Ii, D, D, P, P, P, P]
+        lib.or_cg.argtypes = dims + [P, P, P, Ii, D, D, Ii, P, P, P, P]
         lib.or_rss.argtypes = [L, L, L, Ii, Ii, P, P]
         for f in ("or_fft1d", "or_dft1d_direct", "or_centred1d", "or_centred_nd",
                   "or_E", "or_EH", "or_A", "or_cg", "or_rss"):
@@ -192,8 +192,12 @@ def A(p, maps, mask, lam=0.0, ndim=2):
     return q
 
 
-def cg(y, maps, mask, max_iter, tol=0.0, lam=0.0, ndim=2):
-    """CG-SENSE.  Returns (x [B][...], iters [B], status [B], rho_hist [B][K+1])."""
+def cg(y, maps, mask, max_iter, tol=0.0, lam=0.0, ndim=2, vec32=False):
+    """CG-SENSE.  Returns (x [B][...], iters [B], status [B], rho_hist [B][K+1]).
+
+    vec32=True rounds every CG vector (b, q, x, r, p) to complex64 as it is
+    produced, with the operator and the inner products in fp64: the error
+    floor of complex64 storage alone."""
     y = _c(y)
     nx, ny, nz = _geom(y.shape, ndim)
     nvox = nx * ny * nz
@@ -207,7 +211,7 @@ def cg(y, maps, mask, max_iter, tol=0.0, lam=0.0, ndim=2):
     status = np.zeros(batch, dtype=np.int32)
     hist = np.zeros((batch, max_iter + 1), dtype=np.float64)
     _check(_load().or_cg(nx, ny, nz, ncoils, batch, shared, _ptr(y), _ptr(maps), _ptr(m),
-                         int(max_iter), float(tol), float(lam), _ptr(x), _ptr(iters),
+                         int(max_iter), float(tol), float(lam), int(bool(vec32)), _ptr(x), _ptr(iters),
                          _ptr(status), _ptr(hist)), "cg")
     return x, iters, status, hist
 

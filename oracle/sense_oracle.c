@@ -300,10 +300,29 @@ static cplx dotc(const cplx *a, const cplx *b, long n)
  * rho_hist (per batch element, max_iter + 1 entries) receives rho0 and each
  * rho'; iters[b] the number of completed updates of x; status[b] the reason
  * the loop ended.
+ *
+ * vec32 != 0 stores every CG vector in single precision: b = E^H y, each
+ * q = A p and each new x, r and p are rounded to binary32 components as they
+ * are produced, while the operator, the inner products and alpha, beta stay
+ * in double.  This is the same loop with complex64 storage and exact
+ * arithmetic otherwise: the floor that complex64 storage alone puts under
+ * any fp32 implementation of the solve.
  */
+/* Round both components to the nearest binary32 value (ties to even). */
+static cplx round32(cplx v)
+{
+    return (double)(float)creal(v) + I * (double)(float)cimag(v);
+}
+
+static void round32_vec(cplx *v, long n, int on)
+{
+    if (!on) return;
+    for (long i = 0; i < n; ++i) v[i] = round32(v[i]);
+}
+
 int or_cg(long nx, long ny, long nz, int ncoils, int batch, int maps_shared,
           const cplx *y, const cplx *maps, const uint8_t *mask,
-          int max_iter, double tol, double lambda,
+          int max_iter, double tol, double lambda, int vec32,
           cplx *x, int *iters, int *status, double *rho_hist)
 {
     if (check_dims(nx, ny, nz, ncoils, batch) || max_iter < 0) return -1;
@@ -320,6 +339,7 @@ int or_cg(long nx, long ny, long nz, int ncoils, int batch, int maps_shared,
 
         int rc = or_EH(nx, ny, nz, ncoils, 1, 1, yb, sb, mask, r);
         if (rc) { free(r); return rc; }
+        round32_vec(r, nvox, vec32);
         for (long v = 0; v < nvox; ++v) { xb[v] = 0.0; p[v] = r[v]; }
         double rho = creal(dotc(r, r, nvox)), rho0 = rho;
         hist[0] = rho;
@@ -329,6 +349,7 @@ int or_cg(long nx, long ny, long nz, int ncoils, int batch, int maps_shared,
             if (rho == 0.0) { st = OR_EXACT; break; }
             rc = or_A(nx, ny, nz, ncoils, 1, 1, p, sb, mask, lambda, q);
             if (rc) { free(r); return rc; }
+            round32_vec(q, nvox, vec32);
             double eta = creal(dotc(p, q, nvox));
             if (!isfinite(eta)) { st = OR_NONFINITE; break; }
             if (eta <= 0.0) { st = OR_BREAKDOWN; break; }
@@ -337,6 +358,8 @@ int or_cg(long nx, long ny, long nz, int ncoils, int batch, int maps_shared,
                 xb[v] += alpha * p[v];
                 r[v] -= alpha * q[v];
             }
+            round32_vec(xb, nvox, vec32);
+            round32_vec(r, nvox, vec32);
             double rho_new = creal(dotc(r, r, nvox));
             ++k;
             hist[k] = rho_new;
@@ -344,6 +367,7 @@ int or_cg(long nx, long ny, long nz, int ncoils, int batch, int maps_shared,
             if (tol > 0.0 && sqrt(rho_new / rho0) < tol) { st = OR_CONVERGED; break; }
             double beta = rho_new / rho;
             for (long v = 0; v < nvox; ++v) p[v] = r[v] + beta * p[v];
+            round32_vec(p, nvox, vec32);
             rho = rho_new;
         }
         iters[b] = k;

@@ -11,7 +11,10 @@
   one iteration (alpha = 1) — a special case;
 * stop statuses: zero data -> EXACT at 0, tolerance -> CONVERGED,
   A = 0 (lambda = -1 at full sampling) -> BREAKDOWN, NaN -> NONFINITE;
-* batch elements are independent problems.
+* batch elements are independent problems;
+* the complex64-storage mode (vec32): its iterates are binary32 values, its
+  first iterate differs from the fp64 one by a few binary32 roundings only,
+  and it recovers the image under full sampling to binary32 precision.
 """
 import numpy as np
 import pytest
@@ -152,3 +155,28 @@ def test_gradient_finite_differences(eps):
         fd = (L(x + eps * d) - L(x - eps * d)) / (2 * eps)
         an = np.vdot(g.ravel(), d.ravel()).real
         assert abs(fd - an) <= 1e-8 * max(1.0, abs(an))
+
+
+def test_vec32_iterates_are_binary32_and_close_to_fp64():
+    n, maps, mask, y = _tiny()
+    for k in (1, 6):
+        x32, it32, st32, h32 = oracle.cg(y, maps, mask, k, vec32=True)
+        x64, it64, st64, h64 = oracle.cg(y, maps, mask, k)
+        assert it32[0] == it64[0] == k
+        assert np.array_equal(x32, x32.astype(np.complex64).astype(np.complex128))
+        d = np.linalg.norm(x32 - x64) / np.linalg.norm(x64)
+        assert d > 0.0
+        # one iteration: x1 = alpha * round32(b), a few roundings of 2^-24
+        assert d <= (8 * 2.0 ** -24 if k == 1 else 1e-5)
+    assert not np.array_equal(x64, x64.astype(np.complex64).astype(np.complex128))
+
+
+def test_vec32_full_sampling_recovery():
+    n, nc = 32, 4
+    maps = synth.coil_maps2d(n, nc)
+    full = np.ones(n, np.uint8)
+    x_true = synth.phantom2d(n, seed=5)[None]
+    y = oracle.E(x_true, maps, full)
+    x, iters, status, hist = oracle.cg(y, maps, full, 1, vec32=True)
+    assert iters[0] == 1
+    assert np.linalg.norm(x - x_true) <= 4 * 2.0 ** -24 * np.linalg.norm(x_true)
