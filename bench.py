@@ -172,6 +172,22 @@ def run_serving(args):
         runs.append(dict(rate_factor=f, executor="one-at-a-time", p50_ms=stats.p50 * 1e3,
                          p99_ms=stats.p99 * 1e3, solves_per_s=stats.throughput))
         log(f"serving: x{f} serial p50 {stats.p50*1e3:.2f} ms p99 {stats.p99*1e3:.2f} ms {stats.throughput:.1f}/s")
+    # capacity: all requests present at t = 0
+    burst = make_requests(args.requests, rate=1e9)
+    ex = EngineExecutor(bank, budgets["hbm"], max_slots=128)
+    Scheduler(ex).run(make_requests(32, rate=1e9, seed=98))
+    stats = Scheduler(ex).run(burst)
+    ex.close()
+    runs.append(dict(rate_factor="burst", executor="engine", budget="hbm", p50_ms=stats.p50 * 1e3,
+                     p99_ms=stats.p99 * 1e3, solves_per_s=stats.throughput,
+                     max_inflight=stats.max_inflight, steps=stats.steps))
+    log(f"serving: burst engine p50 {stats.p50*1e3:.2f} ms p99 {stats.p99*1e3:.2f} ms {stats.throughput:.1f}/s "
+        f"inflight<={stats.max_inflight}")
+    burst = make_requests(args.requests, rate=1e9)
+    stats = Scheduler(ser).run(burst)
+    runs.append(dict(rate_factor="burst", executor="one-at-a-time", p50_ms=stats.p50 * 1e3,
+                     p99_ms=stats.p99 * 1e3, solves_per_s=stats.throughput))
+    log(f"serving: burst serial p50 {stats.p50*1e3:.2f} ms p99 {stats.p99*1e3:.2f} ms {stats.throughput:.1f}/s")
     ser.close()
     key = [r for r in runs if r["rate_factor"] == 0.9 and r.get("budget") == "hbm"][0]
     print(json.dumps({"metric": "served recon p99 latency (Poisson arrivals at 0.9 x one-at-a-time rate)",
@@ -185,11 +201,11 @@ def run_serving(args):
 def run_precision(args):
     """384x384, 32 coils, 8 slices, VD R=4, 40 iterations: maps and k-space
     in c64 / bf16 / fp16 storage (fp32 arithmetic, fp64 reductions); solves/s
-    and relative L2 error against the FP64 oracle (raw and quantised inputs)
-    and against the GPU fp32 result, on slice 0."""
+    and the relative L2 difference of each 16-bit result from the GPU
+    complex64 result over all slices.  The errors against the FP64 oracle are
+    the parity test's (tests/test_gpu_precision.py)."""
     import torch
 
-    import oracle
     from paper_1807_11830_amd import sense, synth
 
     w = synth.PREC_384
@@ -215,29 +231,16 @@ def run_precision(args):
                 plan.cg(ys, K, sync=False)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / reps
-            res = plan.cg(ys, K)
-            xs[st] = res.x[0].cpu().numpy().astype(np.complex128)
+            xs[st] = plan.cg(ys, K).x.clone()
             out[st] = {"solve_ms": dt * 1e3, "applies_per_s": B * K / dt}
         log(f"precision: {st} {dt*1e3:.2f} ms/solve")
-    # accuracy on slice 0 against the FP64 oracle
-    y0 = y[0:1].cpu().numpy().astype(np.complex128)
-    m0 = maps[0].astype(np.complex64).astype(np.complex128)
-    t0 = time.perf_counter()
-    xo, _, _, _ = oracle.cg(y0, m0, mask, K)
-    log(f"precision: oracle slice 0 in {time.perf_counter() - t0:.1f} s")
-    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))  # noqa: E731
-    for st in ("c64", "bf16", "fp16"):
-        out[st]["rel_l2_vs_oracle"] = rel(xs[st], xo[0])
-        out[st]["rel_l2_vs_gpu_fp32"] = rel(xs[st], xs["c64"])
-        if st != "c64":
-            dt16 = torch.bfloat16 if st == "bf16" else torch.float16
-            q = lambda a: torch.view_as_complex(  # noqa: E731
-                torch.view_as_real(torch.from_numpy(a.astype(np.complex64))).to(dt16).float().contiguous()
-            ).numpy().astype(np.complex128)
-            xq, _, _, _ = oracle.cg(q(y0), q(m0), mask, K)
-            out[st]["rel_l2_vs_oracle_on_quantised_inputs"] = rel(xs[st], xq[0])
+    for st in ("bf16", "fp16"):
+        d = xs[st] - xs["c64"]
+        out[st]["rel_l2_vs_gpu_c64_max_over_slices"] = float(
+            (torch.linalg.vector_norm(d.reshape(B, -1), dim=1)
+             / torch.linalg.vector_norm(xs["c64"].reshape(B, -1), dim=1)).max())
         log(f"precision: {st} {out[st]}")
-    print(json.dumps({"metric": "E^H E applies/s and rel-L2 vs FP64 oracle by storage precision",
+    print(json.dumps({"metric": "E^H E applies/s by storage precision (CG-SENSE, 40 iterations)",
                       "value": out["bf16"]["applies_per_s"], "unit": "applies/s", "n_gpus": 1,
                       "higher_is_better": True, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": w.name, "slices": B, "iters": K}, "variants": out}), flush=True)
@@ -325,9 +328,11 @@ def run_cgsense(args):
     nvox = w.n * w.n
     C = w.ncoils
     avg_s = ms_l / 1e3 / max(n_l, 1)
-    # fused CG launch: reads S (C values), r and p_old, writes p and q
+    # fused CG launch k: reads S (C values); k = 0 reads p and r and writes
+    # q; k >= 1 also finishes iteration k-1, reading x, r, p, q and writing
+    # x, r, p, q.  Averaged over the K launches of a solve.
     sbytes = 8 if args.maps_storage == "c64" else 4
-    bytes_launch = B * nvox * (sbytes * C + 8 * 4)
+    bytes_launch = B * nvox * (sbytes * C + (8 * 3 + (K - 1) * 8 * 8) / K)
     achieved = bytes_launch / avg_s / 1e9
     applies = B * K * args.steps
     log(f"bench: {dt * 1e3 / args.steps:.2f} ms/step, fused launch avg {avg_s * 1e6:.1f} us "
@@ -362,12 +367,12 @@ def run_cgsense(args):
         "config": {"workload": w.name, "slices": B, "iters": K, "maps": "per-slice",
                    "maps_storage": args.maps_storage, "kspace_storage": "c64",
                    "inner_products": "f64", "nx": w.n, "ny": w.n, "coils": C},
-        "roofline": {"bound": "hbm", "kernel": "ehe2d_kernel (fused E^H E + p update, CG mode)",
+        "roofline": {"bound": "hbm", "kernel": "ehe2d_kernel (fused CG iteration: x, r, p updates + E^H E)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("sense::ehe2d_kernel<256, 0, true>"),
                      "avg_launch_us": avg_s * 1e6, "launches": n_l,
-                     "bytes_per_launch": bytes_launch},
+                     "bytes_per_launch": round(bytes_launch)},
         "ehe_apply": {"avg_launch_us": apply_s * 1e6, "bytes_per_launch": apply_bytes,
                       "achieved_gbs": apply_bytes / apply_s / 1e9,
                       "applies_per_s": B / apply_s},

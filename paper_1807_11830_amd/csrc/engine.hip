@@ -4,10 +4,10 @@
 // single-slice problem with its own plan (maps, mask, workspace, CG state),
 // k-space and output image; admission checks a free slot and a device-memory
 // budget.  A step advances every running slot by one CG iteration with one
-// batched launch of the fused normal operator and one batched update launch
+// batched launch of the fused iteration (previous updates + normal operator)
 // per distinct (ny, maps storage) group: block row i of a batched launch
 // runs problem i of the group's device table, so a problem computes exactly
-// what its own launches would (results are bitwise the same alone or in any
+// what its own launch would (results are bitwise the same alone or in any
 // mix).  Requests admitted between steps start on the next step; finished
 // slots are reported by poll and freed.  Everything is enqueued on the
 // engine's stream; the host never waits for the device except in poll's
@@ -47,11 +47,9 @@ struct sense_engine_s {
   size_t budget = 0;
   size_t used = 0;
   std::vector<Slot> slots;
-  // batched-launch tables: device copies and two pinned staging buffers
+  // batched-launch table: device copy and two pinned staging buffers
   EheParams* d_ehe = nullptr;
-  UpdParams* d_upd = nullptr;
   EheParams* h_ehe[2] = {nullptr, nullptr};
-  UpdParams* h_upd[2] = {nullptr, nullptr};
   hipEvent_t staged[2] = {nullptr, nullptr};
   int buf = 0;
   long steps = 0;
@@ -64,11 +62,9 @@ static void engine_free(sense_engine e) {
     if (s.done) (void)hipEventDestroy(s.done);
   for (int i = 0; i < 2; ++i) {
     if (e->h_ehe[i]) (void)hipHostFree(e->h_ehe[i]);
-    if (e->h_upd[i]) (void)hipHostFree(e->h_upd[i]);
     if (e->staged[i]) (void)hipEventDestroy(e->staged[i]);
   }
   if (e->d_ehe) (void)hipFree(e->d_ehe);
-  if (e->d_upd) (void)hipFree(e->d_upd);
   if (e->st) (void)hipStreamDestroy(e->st);
   delete e;
 }
@@ -86,11 +82,8 @@ sense_status sense_engine_create(size_t budget_bytes, int32_t max_slots, sense_e
   hipError_t err = hipGetDevice(&e->device);
   if (err == hipSuccess) err = hipStreamCreateWithFlags(&e->st, hipStreamNonBlocking);
   if (err == hipSuccess) err = hipMalloc(reinterpret_cast<void**>(&e->d_ehe), sizeof(EheParams) * max_slots);
-  if (err == hipSuccess) err = hipMalloc(reinterpret_cast<void**>(&e->d_upd), sizeof(UpdParams) * max_slots);
   for (int i = 0; i < 2 && err == hipSuccess; ++i) {
     err = hipHostMalloc(reinterpret_cast<void**>(&e->h_ehe[i]), sizeof(EheParams) * max_slots, hipHostMallocDefault);
-    if (err == hipSuccess)
-      err = hipHostMalloc(reinterpret_cast<void**>(&e->h_upd[i]), sizeof(UpdParams) * max_slots, hipHostMallocDefault);
     if (err == hipSuccess) err = hipEventCreateWithFlags(&e->staged[i], hipEventDisableTiming);
   }
   for (auto& s : e->slots)
@@ -138,7 +131,7 @@ sense_status sense_engine_admit(sense_engine e, sense_plan plan, const void* d_y
   const CgArgs cg = plan->cg_args(rel_tol, nullptr, 0);
   hipError_t err = enqueue_solve_begin(plan, d_y, static_cast<c32*>(d_x), cg, e->st);
   if (err == hipSuccess && max_iter == 0) {
-    err = enqueue_solve_end(plan, cg, nullptr, e->st);
+    err = enqueue_solve_end(plan, static_cast<c32*>(d_x), 0, cg, nullptr, e->st);
     if (err == hipSuccess) err = hipEventRecord(sl.done, e->st);
   }
   if (err != hipSuccess) return device_fail(err, "sense_engine_admit");
@@ -178,7 +171,6 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
   const int b = e->buf;
   hipError_t err = hipEventSynchronize(e->staged[b]);
   EheParams* he = e->h_ehe[b];
-  UpdParams* hu = e->h_upd[b];
   int n = 0;
   for (auto& g : groups)
     for (int i : g.second) {
@@ -188,34 +180,28 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
       c32* r = p->at<c32>(p->L.r);
       c32* pv = p->at<c32>(p->L.p);
       c32* q = p->at<c32>(p->L.q);
-      fill_ehe_cg_params(p->g, p->tb, p->maps, r, pv, q, sl.lambda, cg, &he[n]);
-      hu[n] = UpdParams{sl.x, r, pv, q, p->g.nx * p->g.ny * p->g.nz, cg};
+      fill_ehe_cg_params(p->g, p->tb, p->maps, sl.x, r, pv, q, sl.lambda, sl.k, cg, &he[n]);
       ++n;
     }
   if (err == hipSuccess)
     err = hipMemcpyAsync(e->d_ehe, he, sizeof(EheParams) * n, hipMemcpyHostToDevice, e->st);
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(e->d_upd, hu, sizeof(UpdParams) * n, hipMemcpyHostToDevice, e->st);
   if (err == hipSuccess) err = hipEventRecord(e->staged[b], e->st);
   e->buf ^= 1;
 
   int off = 0;
   for (auto& g : groups) {
     const int cnt = (int)g.second.size();
-    int max_tiles = 0, max_rr = 0;
-    for (int j = 0; j < cnt; ++j) {
-      max_tiles = std::max(max_tiles, he[off + j].ntiles);
-      max_rr = std::max(max_rr, hu[off + j].cg.rr_tiles);
-    }
+    int max_tiles = 0;
+    for (int j = 0; j < cnt; ++j) max_tiles = std::max(max_tiles, he[off + j].ntiles);
+    // the fused launch also finishes each problem's previous iteration
     if (err == hipSuccess) err = launch_ehe_table(g.first.first, g.first.second, e->d_ehe + off, cnt, max_tiles, e->st);
-    if (err == hipSuccess) err = launch_cg_update_table(e->d_upd + off, cnt, max_rr, e->st);
     off += cnt;
   }
   for (auto& g : groups)
     for (int i : g.second) {
       Slot& sl = e->slots[(size_t)i];
       if (++sl.k == sl.K && err == hipSuccess) {
-        err = enqueue_solve_end(sl.plan, sl.plan->cg_args(sl.tol, nullptr, 0), nullptr, e->st);
+        err = enqueue_solve_end(sl.plan, sl.x, sl.K, sl.plan->cg_args(sl.tol, nullptr, 0), nullptr, e->st);
         if (err == hipSuccess) err = hipEventRecord(sl.done, e->st);
         sl.finishing = true;
       }

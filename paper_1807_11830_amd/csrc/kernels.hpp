@@ -69,6 +69,11 @@ struct CgArgs {
   double* rr_part;       // [B][rr_tiles]
   int eta_tiles;
   int rr_tiles;
+  // fused 2D iteration: [2][B][part_tiles][4] partials (Re<p,q>, Re<r,q>,
+  // <q,q>, <r,r>), double-buffered by iteration parity
+  double* part4;
+  int part_tiles;
+  int part_batch;
   double* rho_hist;      // optional [B][hist_len]
   int hist_len;
   double tol;
@@ -91,22 +96,16 @@ struct EheParams {
   int ncoils;
   float lambda;
   // CG only
+  c32* x;
   CgState* state;
   const double* rr_part;
   int rr_tiles;
+  double* part4;
+  int part_batch;
+  int k;             // iteration index of this launch
   double* rho_hist;
   int hist_len;
   double tol;
-};
-
-// Arguments of one problem of the batched CG update.
-struct UpdParams {
-  c32* x;
-  c32* r;
-  const c32* p;
-  const c32* q;
-  long nvox;
-  CgArgs cg;
 };
 
 // Supported transform lengths (compile-time instantiations).
@@ -119,9 +118,16 @@ int cg_tiles(long nvox);
 // Launchers; return hipSuccess or the launch error.
 hipError_t launch_ehe(const Geom& g, const Tables& tb, const void* maps, const c32* p, c32* q,
                       float lambda, double* eta_part, hipStream_t st);
-hipError_t launch_ehe_cg(const Geom& g, const Tables& tb, const void* maps, const c32* r, c32* p,
-                         c32* q, float lambda, const CgArgs& cg, hipStream_t st);
-hipError_t launch_cg_init(const Geom& g, const c32* b, c32* x, c32* r, c32* p,
+// Fused CG iteration k (2D): finishes iteration k-1 (x, r, p updates) and
+// computes q = A p with the partials of the next scalars.
+hipError_t launch_ehe_cg(const Geom& g, const Tables& tb, const void* maps, c32* x, c32* r, c32* p,
+                         c32* q, float lambda, int k, const CgArgs& cg, hipStream_t st);
+// After K fused iterations: x, r updates of iteration K-1 and <r, r>.
+hipError_t launch_cg_fused_final(const Geom& g, c32* x, c32* r, const c32* p, const c32* q, int K,
+                                 const CgArgs& cg, hipStream_t st);
+// x = 0, r = p = b, q = 0 (q may be null), the <r, r> partials and a fresh
+// CgState per batch element.
+hipError_t launch_cg_init(const Geom& g, const c32* b, c32* x, c32* r, c32* p, c32* q,
                           const CgArgs& cg, hipStream_t st);
 hipError_t launch_cg_update(const Geom& g, c32* x, c32* r, const c32* p, const c32* q,
                             const CgArgs& cg, hipStream_t st);
@@ -129,11 +135,11 @@ hipError_t launch_cg_finish(const Geom& g, const CgArgs& cg, CgInfo* info, CgInf
 hipError_t launch_cg_pupdate(const Geom& g, const c32* r, c32* p, const CgArgs& cg, hipStream_t st);
 
 // Batched CG iteration over single-slice problems (serving engine).
-void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, const c32* r, c32* p, c32* q,
-                        float lambda, const CgArgs& cg, EheParams* out);
+void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, c32* x, c32* r, c32* p, c32* q,
+                        float lambda, int k, const CgArgs& cg, EheParams* out);
 hipError_t launch_ehe_table(long ny, int maps_storage, const EheParams* d_table, int nproblems, int max_tiles,
                             hipStream_t st);
-hipError_t launch_cg_update_table(const UpdParams* d_table, int nproblems, int max_tiles, hipStream_t st);
+
 
 // Full-grid forward and adjoint operators (2D).
 hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32* x, c32* work,

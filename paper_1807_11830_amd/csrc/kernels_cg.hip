@@ -30,7 +30,7 @@ struct alignas(16) c32x2 {
 
 __global__ void __launch_bounds__(CG_NT) cg_init_kernel(const c32* __restrict__ bvec, c32* __restrict__ x,
                                                         c32* __restrict__ r, c32* __restrict__ p,
-                                                        long nvox, CgArgs cg) {
+                                                        c32* __restrict__ q, long nvox, CgArgs cg) {
   __shared__ double red[CG_NT / 64];
   const int b = blockIdx.y;
   const long base = (long)b * nvox + (long)blockIdx.x * CG_CHUNK;
@@ -44,6 +44,7 @@ __global__ void __launch_bounds__(CG_NT) cg_init_kernel(const c32* __restrict__ 
       if (r != bvec) *reinterpret_cast<c32x2*>(r + i) = v;
       *reinterpret_cast<c32x2*>(p + i) = v;
       *reinterpret_cast<c32x2*>(x + i) = c32x2{{0.f, 0.f}, {0.f, 0.f}};
+      if (q) *reinterpret_cast<c32x2*>(q + i) = c32x2{{0.f, 0.f}, {0.f, 0.f}};
       acc += (double)v.a.re * v.a.re + (double)v.a.im * v.a.im + (double)v.b.re * v.b.re +
              (double)v.b.im * v.b.im;
     }
@@ -115,19 +116,6 @@ __global__ void __launch_bounds__(CG_NT) cg_update_kernel(c32* __restrict__ x, c
   cg_update_body(x, r, p, q, nvox, cg, blockIdx.y, blockIdx.x);
 }
 
-// Batched update: block row blockIdx.y updates problem table[blockIdx.y].
-__global__ void __launch_bounds__(CG_NT) cg_update_table_kernel(const UpdParams* __restrict__ table) {
-  const UpdParams U = table[blockIdx.y];
-  if ((long)blockIdx.x >= (long)U.cg.rr_tiles) return;
-  cg_update_body(U.x, U.r, U.p, U.q, U.nvox, U.cg, 0, blockIdx.x);
-}
-
-hipError_t launch_cg_update_table(const UpdParams* d_table, int nproblems, int max_tiles, hipStream_t st) {
-  hipLaunchKernelGGL(cg_update_table_kernel, dim3((unsigned)max_tiles, (unsigned)nproblems), dim3(CG_NT), 0,
-                     st, d_table);
-  return hipGetLastError();
-}
-
 __global__ void cg_finish_kernel(CgArgs cg, CgInfo* info, CgInfo* info2) {
   const int b = blockIdx.x;
   if (threadIdx.x != 0) return;
@@ -184,6 +172,56 @@ __global__ void __launch_bounds__(CG_NT) cg_pupdate_kernel(const c32* __restrict
   }
 }
 
+// Last step of the fused 2D iteration: launch K's scalar logic, then
+// x += alpha p, r -= alpha q and the partials of <r, r> for the final test.
+__global__ void __launch_bounds__(CG_NT) cg_fused_final_kernel(c32* __restrict__ x, c32* __restrict__ r,
+                                                               const c32* __restrict__ p,
+                                                               const c32* __restrict__ q, long nvox, int K,
+                                                               CgArgs cg) {
+  __shared__ double red[CG_NT / 64];
+  const int b = blockIdx.y;
+  CgFused o;
+  if (!cg_fused_begin(cg.state + b, cg.rr_part, cg.rr_tiles, cg.part4, cg.part_batch, cg.part_tiles,
+                      cg.rho_hist, cg.hist_len, cg.tol, K, b, blockIdx.x == 0 && threadIdx.x == 0, o))
+    return;
+  const double alpha = o.alpha;
+  const long base = (long)b * nvox + (long)blockIdx.x * CG_CHUNK;
+  const long lim = (long)b * nvox + nvox;
+  double acc = 0.0;
+#pragma unroll
+  for (int s = 0; s < CG_STEPS; ++s) {
+    const long i = base + ((long)s * CG_NT + threadIdx.x) * CG_VEC;
+    if (i < lim) {
+      c32x2 xv = *reinterpret_cast<const c32x2*>(x + i);
+      c32x2 rv = *reinterpret_cast<const c32x2*>(r + i);
+      const c32x2 pv = *reinterpret_cast<const c32x2*>(p + i);
+      const c32x2 qv = *reinterpret_cast<const c32x2*>(q + i);
+      xv.a.re = (float)((double)xv.a.re + alpha * pv.a.re);
+      xv.a.im = (float)((double)xv.a.im + alpha * pv.a.im);
+      xv.b.re = (float)((double)xv.b.re + alpha * pv.b.re);
+      xv.b.im = (float)((double)xv.b.im + alpha * pv.b.im);
+      rv.a.re = (float)((double)rv.a.re - alpha * qv.a.re);
+      rv.a.im = (float)((double)rv.a.im - alpha * qv.a.im);
+      rv.b.re = (float)((double)rv.b.re - alpha * qv.b.re);
+      rv.b.im = (float)((double)rv.b.im - alpha * qv.b.im);
+      *reinterpret_cast<c32x2*>(x + i) = xv;
+      *reinterpret_cast<c32x2*>(r + i) = rv;
+      acc += (double)rv.a.re * rv.a.re + (double)rv.a.im * rv.a.im + (double)rv.b.re * rv.b.re +
+             (double)rv.b.im * rv.b.im;
+    }
+  }
+  const double tot = block_sum<CG_NT>(acc, red);
+  if (threadIdx.x == 0) cg.rr_part[(long)b * cg.rr_tiles + blockIdx.x] = tot;
+}
+
+hipError_t launch_cg_fused_final(const Geom& g, c32* x, c32* r, const c32* p, const c32* q, int K,
+                                 const CgArgs& cg, hipStream_t st) {
+  const long nvox = g.nx * g.ny * g.nz;
+  dim3 grid((unsigned)cg_tiles(nvox), (unsigned)g.batch);
+  hipLaunchKernelGGL(cg_fused_final_kernel, grid, dim3(CG_NT), 0, st, x, r, p, q, nvox, K, cg);
+  return hipGetLastError();
+}
+
 hipError_t launch_cg_pupdate(const Geom& g, const c32* r, c32* p, const CgArgs& cg, hipStream_t st) {
   const long nvox = g.nx * g.ny * g.nz;
   dim3 grid((unsigned)cg_tiles(nvox), (unsigned)g.batch);
@@ -191,11 +229,11 @@ hipError_t launch_cg_pupdate(const Geom& g, const c32* r, c32* p, const CgArgs& 
   return hipGetLastError();
 }
 
-hipError_t launch_cg_init(const Geom& g, const c32* bvec, c32* x, c32* r, c32* p, const CgArgs& cg,
+hipError_t launch_cg_init(const Geom& g, const c32* bvec, c32* x, c32* r, c32* p, c32* q, const CgArgs& cg,
                           hipStream_t st) {
   const long nvox = g.nx * g.ny * g.nz;
   dim3 grid((unsigned)cg_tiles(nvox), (unsigned)g.batch);
-  hipLaunchKernelGGL(cg_init_kernel, grid, dim3(CG_NT), 0, st, bvec, x, r, p, nvox, cg);
+  hipLaunchKernelGGL(cg_init_kernel, grid, dim3(CG_NT), 0, st, bvec, x, r, p, q, nvox, cg);
   return hipGetLastError();
 }
 

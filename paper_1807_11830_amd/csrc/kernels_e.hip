@@ -176,9 +176,11 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) colpass_ker
       const Buf bw = make_buf(P.src + bc * nvox, vbytes);
 #pragma unroll
       for (int j = 0; j < E; ++j) {
+        // masked-out lines are not read at all (no memory request)
         const bool on = MODE == CM_ADJ && P.mask_load ? mask_at(t + T * j) : true;
-        const c32 v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
-        u[j] = on ? cscale(v, sgn) : c32{0.f, 0.f};
+        c32 v = {0.f, 0.f};
+        if (on) v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
+        u[j] = cscale(v, sgn);
       }
     }
     if constexpr (MODE == CM_ADJ) {
@@ -214,8 +216,9 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) colpass_ker
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const bool on = P.mask_load ? mask_at(t + T * j) : true;
-        const c32 v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
-        u[j] = on ? cscale(v, sgn) : c32{0.f, 0.f};
+        c32 v = {0.f, 0.f};
+        if (on) v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
+        u[j] = cscale(v, sgn);
       }
       fft_line_sb<N, T, +1>(u, t, twt, lv, Rad{});
       const Buf bs = make_buf(static_cast<const SType*>(P.maps) + b * P.maps_bstride + (long)c * nvox,

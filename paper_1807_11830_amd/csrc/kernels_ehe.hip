@@ -51,10 +51,11 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   const bool valid = x < P.nx;
   const long nx = P.nx;
 
-  double beta = 0.0;
+  // CG: the start-of-iteration scalars (every block derives the same ones)
+  [[maybe_unused]] CgFused cgs{};
   if constexpr (CG) {
-    if (!cg_iteration_begin(P.state + b, P.rr_part, P.rr_tiles, P.rho_hist, P.hist_len, P.tol, b,
-                            tile == 0 && tid == 0, beta))
+    if (!cg_fused_begin(P.state + b, P.rr_part, P.rr_tiles, P.part4, P.part_batch, P.ntiles, P.rho_hist,
+                        P.hist_len, P.tol, P.k, b, tile == 0 && tid == 0, cgs))
       return;
   }
 
@@ -72,25 +73,88 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   const uint32_t rstep = (uint32_t)T * (uint32_t)nx;      // rows t -> t + T
   const uint32_t img_bytes = (uint32_t)(nvox * (long)sizeof(c32));
   const Buf bq = make_buf(P.q + (long)b * nvox, img_bytes);
+#ifndef SENSE_EHE_RREG
+#define SENSE_EHE_RREG 0
+#endif
+  // CG keeps the new residual in registers for Re<r, q> (RREG), or re-reads
+  // the tile it wrote (fewer VGPRs, one more pass over r through the caches)
+  constexpr bool RREG = SENSE_EHE_RREG != 0;
   c32 p[E], q[E];
-  {
+  [[maybe_unused]] c32 r[RREG ? E : 1];
+  [[maybe_unused]] double rho_acc = 0.0;
+  if constexpr (!CG) {
     const Buf bp = make_buf(P.p_in + (long)b * nvox, img_bytes);
-    [[maybe_unused]] Buf br, bpo;
-    if constexpr (CG) {
-      br = make_buf(P.r + (long)b * nvox, img_bytes);
-      bpo = make_buf(P.p_out + (long)b * nvox, img_bytes);
-    }
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      c32 v = buf_load_c64(bp, voff * 8u, (uint32_t)j * rstep * 8u);
-      if constexpr (CG) {
-        const c32 rv = buf_load_c64(br, voff * 8u, (uint32_t)j * rstep * 8u);
-        v = {(float)((double)rv.re + beta * (double)v.re),
-             (float)((double)rv.im + beta * (double)v.im)};
-        if (valid) buf_store_c64(bpo, v, voff * 8u, (uint32_t)j * rstep * 8u);
-      }
-      p[j] = v;
+      p[j] = buf_load_c64(bp, voff * 8u, (uint32_t)j * rstep * 8u);
       q[j] = {0.f, 0.f};
+    }
+  } else {
+    // iteration k > 0 first finishes iteration k-1:
+    //   x += alpha p,  r -= alpha q,  p = r + beta p
+    const Buf bp = make_buf(P.p_out + (long)b * nvox, img_bytes);
+    const Buf br = make_buf(P.r + (long)b * nvox, img_bytes);
+    const Buf bx = make_buf(P.x + (long)b * nvox, img_bytes);
+    // Groups of G rows in a two-slot software pipeline: the loads of group
+    // g+1 are issued before group g is updated and stored, so a wait for
+    // group g never includes the stores of the group before it, and at most
+    // two groups of loads hold registers (the transform's are still free).
+    // Launch 0 runs the same code: alpha = beta = 0 and q is zero there
+    // (the init kernel clears it), so the update leaves x, r, p as they are.
+#ifndef SENSE_EHE_PIPE
+#define SENSE_EHE_PIPE 1
+#endif
+    constexpr int G = E % 4 == 0 ? 4 : 1;
+    constexpr int NG = E / G;
+    const uint32_t lo = voff * 8u;
+    const double a = cgs.alpha, bt = cgs.beta;
+    c32 lp[2][G], lr[2][G], lq[2][G], lx[2][G];
+    auto load_group = [&](auto gc, int slot) {
+      constexpr int g0 = decltype(gc)::value * G;
+      sfor<G>([&](auto jc) {
+        constexpr int i = decltype(jc)::value;
+        const uint32_t so = (uint32_t)(g0 + i) * rstep * 8u;
+        lp[slot][i] = buf_load_c64(bp, lo, so);
+        lr[slot][i] = buf_load_c64(br, lo, so);
+        lq[slot][i] = buf_load_c64(bq, lo, so);
+        lx[slot][i] = buf_load_c64(bx, lo, so);
+      });
+    };
+    auto update_group = [&](auto gc, int slot) {
+      constexpr int g0 = decltype(gc)::value * G;
+      sfor<G>([&](auto jc) {
+        constexpr int i = decltype(jc)::value;
+        constexpr int j = g0 + i;
+        const uint32_t so = (uint32_t)j * rstep * 8u;
+        const c32 pv0 = lp[slot][i], qv = lq[slot][i], xv0 = lx[slot][i];
+        const c32 xv = {(float)((double)xv0.re + a * pv0.re), (float)((double)xv0.im + a * pv0.im)};
+        const c32 rv = {(float)((double)lr[slot][i].re - a * qv.re), (float)((double)lr[slot][i].im - a * qv.im)};
+        const c32 pv = {(float)((double)rv.re + bt * pv0.re), (float)((double)rv.im + bt * pv0.im)};
+        if (valid) {
+          buf_store_c64(bx, xv, lo, so);
+          buf_store_c64(br, rv, lo, so);
+          buf_store_c64(bp, pv, lo, so);
+        }
+        p[j] = pv;
+        if constexpr (RREG) r[j] = rv;
+        else if (valid) rho_acc += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+        q[j] = {0.f, 0.f};
+      });
+    };
+    if constexpr (SENSE_EHE_PIPE != 0 && NG > 1) {
+      load_group(std::integral_constant<int, 0>{}, 0);
+      sfor<NG>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if constexpr (g + 1 < NG) load_group(std::integral_constant<int, g + 1>{}, (g + 1) & 1);
+        asm volatile("" ::: "memory");
+        update_group(gc, g & 1);
+      });
+    } else {
+      sfor<NG>([&](auto gc) {
+        load_group(gc, 0);
+        update_group(gc, 0);
+        asm volatile("" ::: "memory");
+      });
     }
   }
   __syncthreads();
@@ -149,18 +213,54 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   }
 #endif
 
-  double eta = 0.0;
+  if constexpr (!CG) {
+    double eta = 0.0;
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
-    c32 qq = {q[j].re + P.lambda * p[j].re, q[j].im + P.lambda * p[j].im};
-    if (valid) {
-      buf_store_c64(bq, qq, voff * 8u, (uint32_t)j * rstep * 8u);
-      eta += (double)p[j].re * (double)qq.re + (double)p[j].im * (double)qq.im;
+    for (int j = 0; j < E; ++j) {
+      c32 qq = {q[j].re + P.lambda * p[j].re, q[j].im + P.lambda * p[j].im};
+      if (valid) {
+        buf_store_c64(bq, qq, voff * 8u, (uint32_t)j * rstep * 8u);
+        eta += (double)p[j].re * (double)qq.re + (double)p[j].im * (double)qq.im;
+      }
     }
-  }
-  if (P.eta_part) {
-    const double tot = block_sum<NT>(eta, red);
-    if (tid == 0) P.eta_part[(long)b * P.ntiles + tile] = tot;
+    if (P.eta_part) {
+      const double tot = block_sum<NT>(eta, red);
+      if (tid == 0) P.eta_part[(long)b * P.ntiles + tile] = tot;
+    }
+  } else {
+    // q = A p; fp64 partials of Re<p,q>, Re<r,q>, <q,q>, <r,r> for the
+    // next launch (alpha, the recurrence for beta, and the true rho_k)
+    double acc[4] = {0.0, 0.0, 0.0, rho_acc};
+    // the residual written by the prologue, re-read (all loads before the
+    // first q store, so no wait covers a store)
+    c32 rr[RREG ? 1 : E];
+    if constexpr (!RREG) {
+      const Buf brr = make_buf(P.r + (long)b * nvox, img_bytes);
+#pragma unroll
+      for (int j = 0; j < E; ++j) rr[j] = buf_load_c64(brr, voff * 8u, (uint32_t)j * rstep * 8u);
+      asm volatile("" ::: "memory");
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      c32 qq = {q[j].re + P.lambda * p[j].re, q[j].im + P.lambda * p[j].im};
+      c32 rv;
+      if constexpr (RREG) rv = r[j];
+      else rv = rr[j];
+      if (valid) {
+        buf_store_c64(bq, qq, voff * 8u, (uint32_t)j * rstep * 8u);
+        acc[0] += (double)p[j].re * (double)qq.re + (double)p[j].im * (double)qq.im;
+        acc[1] += (double)rv.re * (double)qq.re + (double)rv.im * (double)qq.im;
+        acc[2] += (double)qq.re * (double)qq.re + (double)qq.im * (double)qq.im;
+        if constexpr (RREG) acc[3] += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+      }
+    }
+    double* out = P.part4 + (((long)(P.k & 1) * P.part_batch + b) * P.ntiles + tile) * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double tot = block_sum<NT>(acc[i], red);
+      if (tid == 0) out[i] = tot;
+      if constexpr (NT / 64 > 1) __syncthreads();  // red is reused
+    }
   }
 }
 
@@ -216,11 +316,15 @@ static hipError_t launch_ehe_impl(const Geom& g, const Tables& tb, EheParams P, 
   return err;
 }
 
-void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, const c32* r, c32* p, c32* q,
-                        float lambda, const CgArgs& cg, EheParams* out) {
+void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, c32* x, c32* r, c32* p, c32* q,
+                        float lambda, int k, const CgArgs& cg, EheParams* out) {
   EheParams P{};
   P.maps = maps;
+  P.x = x;
   P.r = r;
+  P.k = k;
+  P.part4 = cg.part4;
+  P.part_batch = cg.part_batch;
   P.p_in = p;
   P.p_out = p;
   P.q = q;
@@ -270,22 +374,10 @@ hipError_t launch_ehe(const Geom& g, const Tables& tb, const void* maps, const c
   return launch_ehe_impl<false>(g, tb, P, st);
 }
 
-hipError_t launch_ehe_cg(const Geom& g, const Tables& tb, const void* maps, const c32* r, c32* p,
-                         c32* q, float lambda, const CgArgs& cg, hipStream_t st) {
+hipError_t launch_ehe_cg(const Geom& g, const Tables& tb, const void* maps, c32* x, c32* r, c32* p,
+                         c32* q, float lambda, int k, const CgArgs& cg, hipStream_t st) {
   EheParams P{};
-  P.maps = maps;
-  P.r = r;
-  P.p_in = p;
-  P.p_out = p;
-  P.q = q;
-  P.lambda = lambda;
-  P.eta_part = cg.eta_part;
-  P.state = cg.state;
-  P.rr_part = cg.rr_part;
-  P.rr_tiles = cg.rr_tiles;
-  P.rho_hist = cg.rho_hist;
-  P.hist_len = cg.hist_len;
-  P.tol = cg.tol;
+  fill_ehe_cg_params(g, tb, maps, x, r, p, q, lambda, k, cg, &P);
   return launch_ehe_impl<true>(g, tb, P, st);
 }
 

@@ -78,6 +78,33 @@ struct EheLen<128> {
   using R = Radices<8, 4, 4>;
   static constexpr int TX = 16;
 };
+// 384 = 12 * 4 * 4 * 2 over 32 threads per column: 12 elements per thread
+// instead of 24 keeps the kernel within 3 waves per SIMD, and twice the
+// threads per column fill the chip at small batches.
+#ifndef SENSE_EHE384_T
+#define SENSE_EHE384_T 32
+#endif
+#if SENSE_EHE384_T == 32
+template <>
+struct EheLen<384> {
+  static constexpr int T = 32;
+  static constexpr int E = 12;
+  using R = Radices<12, 4, 4, 2>;
+  static constexpr int TX = 8;
+};
+#endif
+#ifndef SENSE_EHE320_T
+#define SENSE_EHE320_T 16
+#endif
+#if SENSE_EHE320_T == 32
+template <>
+struct EheLen<320> {
+  static constexpr int T = 32;
+  static constexpr int E = 10;
+  using R = Radices<10, 2, 2, 2, 2, 2>;
+  static constexpr int TX = 8;
+};
+#endif
 template <>
 struct EheLen<192> {
   static constexpr int T = 16;

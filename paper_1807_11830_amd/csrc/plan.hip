@@ -68,6 +68,7 @@ static Layout make_layout(const sense_desc& d) {
   L.state = take(sizeof(CgState) * B);
   L.eta_part = take(sizeof(double) * B * (size_t)L.eta_tiles);
   L.rr_part = take(sizeof(double) * B * (size_t)L.rr_tiles);
+  L.part4 = take(sizeof(double) * 2 * B * (size_t)L.eta_tiles * 4);
   L.info = take(sizeof(CgInfo) * B);
   L.total = off;
   return L;
@@ -139,11 +140,11 @@ hipError_t enqueue_solve_begin(sense_plan p, const void* d_y, c32* x, const CgAr
                                       hipStream_t st) {
   c32* r = p->at<c32>(p->L.r);
   hipError_t e = launch_EH(p->g, p->tb, p->maps, d_y, p->at<c32>(p->L.work), r, st);
-  if (e == hipSuccess) e = launch_cg_init(p->g, r, x, r, p->at<c32>(p->L.p), cg, st);
+  if (e == hipSuccess) e = launch_cg_init(p->g, r, x, r, p->at<c32>(p->L.p), p->at<c32>(p->L.q), cg, st);
   return e;
 }
 
-hipError_t enqueue_iteration(sense_plan p, c32* x, float lambda, const CgArgs& cg, hipStream_t st) {
+hipError_t enqueue_iteration(sense_plan p, c32* x, float lambda, int k, const CgArgs& cg, hipStream_t st) {
   c32* r = p->at<c32>(p->L.r);
   c32* pv = p->at<c32>(p->L.p);
   c32* q = p->at<c32>(p->L.q);
@@ -154,23 +155,29 @@ hipError_t enqueue_iteration(sense_plan p, c32* x, float lambda, const CgArgs& c
     e = launch_cg_pupdate(p->g, r, pv, cg, st);
     if (e == hipSuccess)
       e = launch_EHE_composed(p->g, p->tb, p->maps, pv, q, p->at<c32>(p->L.work), lambda, cg.eta_part, st);
+    if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
+    if (e == hipSuccess) e = launch_cg_update(p->g, x, r, pv, q, cg, st);
   } else {
-    e = launch_ehe_cg(p->g, p->tb, p->maps, r, pv, q, lambda, cg, st);
+    // one launch: the updates of iteration k-1 fused in front of q = A p
+    e = launch_ehe_cg(p->g, p->tb, p->maps, x, r, pv, q, lambda, k, cg, st);
+    if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
   }
-  if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
-  if (e == hipSuccess) e = launch_cg_update(p->g, x, r, pv, q, cg, st);
   return e;
 }
 
-hipError_t enqueue_solve_end(sense_plan p, const CgArgs& cg, CgInfo* d_info, hipStream_t st) {
-  return launch_cg_finish(p->g, cg, p->at<CgInfo>(p->L.info), d_info, st);
+hipError_t enqueue_solve_end(sense_plan p, c32* x, int K, const CgArgs& cg, CgInfo* d_info, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (p->d.ndim != 3 && K > 0)
+    e = launch_cg_fused_final(p->g, x, p->at<c32>(p->L.r), p->at<c32>(p->L.p), p->at<c32>(p->L.q), K, cg, st);
+  if (e == hipSuccess) e = launch_cg_finish(p->g, cg, p->at<CgInfo>(p->L.info), d_info, st);
+  return e;
 }
 
 static hipError_t enqueue_solve(sense_plan p, const void* d_y, c32* x, int32_t max_iter, float lambda,
                                 const CgArgs& cg, CgInfo* d_info, hipStream_t st) {
   hipError_t e = enqueue_solve_begin(p, d_y, x, cg, st);
-  for (int k = 0; k < max_iter && e == hipSuccess; ++k) e = enqueue_iteration(p, x, lambda, cg, st);
-  if (e == hipSuccess) e = enqueue_solve_end(p, cg, d_info, st);
+  for (int k = 0; k < max_iter && e == hipSuccess; ++k) e = enqueue_iteration(p, x, lambda, k, cg, st);
+  if (e == hipSuccess) e = enqueue_solve_end(p, x, max_iter, cg, d_info, st);
   return e;
 }
 

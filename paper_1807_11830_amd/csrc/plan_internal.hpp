@@ -14,7 +14,7 @@ namespace sense {
 struct Layout {
   size_t tw_x, tw_y, tw_z, mu_y, mask_c, rows_s, rows_u;
   size_t work, r, p, q;
-  size_t state, eta_part, rr_part, info;
+  size_t state, eta_part, rr_part, part4, info;
   size_t total;
   int eta_tiles, rr_tiles;
 };
@@ -72,6 +72,9 @@ struct sense_plan_s {
     a.rr_part = at<double>(L.rr_part);
     a.eta_tiles = L.eta_tiles;
     a.rr_tiles = L.rr_tiles;
+    a.part4 = at<double>(L.part4);
+    a.part_tiles = L.eta_tiles;
+    a.part_batch = d.batch;
     a.rho_hist = hist;
     a.hist_len = hist_len;
     a.tol = tol;
@@ -84,5 +87,7 @@ sense_status check_solve_args(sense_plan p, const void* d_y, void* d_x, int32_t 
                               double lambda);
 hipError_t enqueue_solve_begin(sense_plan p, const void* d_y, sense::c32* x, const sense::CgArgs& cg,
                                hipStream_t st);
-hipError_t enqueue_iteration(sense_plan p, sense::c32* x, float lambda, const sense::CgArgs& cg, hipStream_t st);
-hipError_t enqueue_solve_end(sense_plan p, const sense::CgArgs& cg, sense::CgInfo* d_info, hipStream_t st);
+hipError_t enqueue_iteration(sense_plan p, sense::c32* x, float lambda, int k, const sense::CgArgs& cg,
+                             hipStream_t st);
+hipError_t enqueue_solve_end(sense_plan p, sense::c32* x, int K, const sense::CgArgs& cg, sense::CgInfo* d_info,
+                             hipStream_t st);
