@@ -190,6 +190,25 @@ SENSE_API sense_status sense_cg_solve(sense_plan plan, const void* d_y, void* d_
  */
 SENSE_API sense_status sense_plan_set_graphs(sense_plan plan, int32_t enable);
 
+/*
+ * Coil groups of the 2D normal operator.  The fused kernel runs one block
+ * per (column tile, batch element); when there are too few of those to fill
+ * the GPU, the plan splits the coils into G contiguous groups, one block per
+ * group, and a combine pass adds the G partial coil sums in group order.
+ * The plan chooses G at creation from its shape (1 when tiles x batch >=
+ * 512, else ceil(512 / (tiles x batch)) capped at coils / 2 and 16) and
+ * sizes its workspace for it.
+ *   sense_plan_set_coil_groups: groups = 0 restores the plan's choice;
+ *     1 <= groups <= that choice forces a smaller split (1 = no split).
+ *     Larger values return SENSE_ERR_UNSUPPORTED.  Results depend on G only
+ *     through the order of the coil sum (deterministic for a given G).
+ *   sense_plan_coil_groups: the current G and the largest allowed (either
+ *     output may be NULL).
+ * 3D plans always use one group.
+ */
+SENSE_API sense_status sense_plan_set_coil_groups(sense_plan plan, int32_t groups);
+SENSE_API sense_status sense_plan_coil_groups(sense_plan plan, int32_t* groups, int32_t* max_groups);
+
 /* Copy the last sense_cg_solve result of every batch element to host memory
  * h_info[B]; synchronises the stream. */
 SENSE_API sense_status sense_plan_cg_info(sense_plan plan, sense_cg_info* h_info, void* stream);

@@ -5,10 +5,11 @@
 // k-space and output image; admission checks a free slot and a device-memory
 // budget.  A step advances every running slot by one CG iteration with one
 // batched launch of the fused iteration (previous updates + normal operator)
-// per distinct (ny, maps storage) group: block row i of a batched launch
-// runs problem i of the group's device table, so a problem computes exactly
-// what its own launch would (results are bitwise the same alone or in any
-// mix).  Requests admitted between steps start on the next step; finished
+// per distinct (ny, maps storage) group, followed by one combine launch
+// when a problem of the group splits its coils: block row i of a batched
+// launch runs problem i of the group's device table with its plan's own
+// coil groups, so a problem computes exactly what its own launch would
+// (results are bitwise the same alone or in any mix).  Requests admitted between steps start on the next step; finished
 // slots are reported by poll and freed.  Everything is enqueued on the
 // engine's stream; the host never waits for the device except in poll's
 // event queries and the reuse of a table staging buffer.
@@ -177,10 +178,7 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
       Slot& sl = e->slots[(size_t)i];
       sense_plan p = sl.plan;
       const CgArgs cg = p->cg_args(sl.tol, nullptr, 0);
-      c32* r = p->at<c32>(p->L.r);
-      c32* pv = p->at<c32>(p->L.p);
-      c32* q = p->at<c32>(p->L.q);
-      fill_ehe_cg_params(p->g, p->tb, p->maps, sl.x, r, pv, q, sl.lambda, sl.k, cg, &he[n]);
+      fill_ehe_cg_params(p->g, p->tb, p->maps, p->vectors(sl.x), sl.lambda, sl.k, cg, &he[n]);
       ++n;
     }
   if (err == hipSuccess)
@@ -191,10 +189,17 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
   int off = 0;
   for (auto& g : groups) {
     const int cnt = (int)g.second.size();
-    int max_tiles = 0;
-    for (int j = 0; j < cnt; ++j) max_tiles = std::max(max_tiles, he[off + j].ntiles);
+    int max_tiles = 0, max_groups = 1, max_ctiles = 0;
+    for (int j = 0; j < cnt; ++j) {
+      const EheParams& P = he[off + j];
+      max_tiles = std::max(max_tiles, P.ntiles);
+      max_groups = std::max(max_groups, P.ngroups);
+      if (P.ngroups > 1) max_ctiles = std::max(max_ctiles, P.part_tiles);
+    }
     // the fused launch also finishes each problem's previous iteration
-    if (err == hipSuccess) err = launch_ehe_table(g.first.first, g.first.second, e->d_ehe + off, cnt, max_tiles, e->st);
+    if (err == hipSuccess)
+      err = launch_ehe_table(g.first.first, g.first.second, e->d_ehe + off, cnt, max_tiles, max_groups, e->st);
+    if (err == hipSuccess && max_groups > 1) err = launch_combine_table(e->d_ehe + off, cnt, max_ctiles, e->st);
     off += cnt;
   }
   for (auto& g : groups)

@@ -80,18 +80,33 @@ struct CgArgs {
 };
 
 // Arguments of the fused 2D normal-operator kernel (one launch, or one row
-// of a batched table launch).
+// of a batched table launch) and of its coil-group combine pass.
+//
+// Coil groups: with ngroups = G > 1 the coils are split into G contiguous
+// ranges, one block per (column tile, batch element, group); each block
+// writes its partial sum over its coils to qpart[g][b] and the combine pass
+// adds the G partials in group order (deterministic), adds lambda p and
+// emits the partials of the scalars.  G = 1 does all of it in one launch.
+//
+// CG vectors r and p are double-buffered: launch k reads r_in, p_in
+// (iterate k-1) and writes r_out, p_out (iterate k), so blocks of other
+// coil groups never see a half-updated vector.
 struct EheParams {
   const void* maps;
-  const c32* r;      // CG: residual (p = r + beta p_old); apply: unused
-  const c32* p_in;   // apply: p; CG: p_old
-  c32* p_out;        // CG: new p (same buffer as p_in)
-  c32* q;
+  const c32* r;      // CG: r_(k-1) (input of the update); apply: unused
+  c32* r_out;        // CG: r_k
+  const c32* p_in;   // apply: p; CG: p_(k-1)
+  c32* p_out;        // CG: p_k
+  c32* q;            // A p (CG: also q_(k-1) on input)
+  c32* qpart;        // G > 1: [G][qpart_gstride] partial coil sums
+  long qpart_gstride;  // elements between groups (batch * nvox)
+  int ngroups;
   const c32* tw;     // [ny]
   const float* mu;   // [ny]
   double* eta_part;  // [B][ntiles] or null
   int ntiles;        // column tiles of one batch element
   long nx;
+  long nvox;
   long maps_bstride;
   int ncoils;
   float lambda;
@@ -102,10 +117,21 @@ struct EheParams {
   int rr_tiles;
   double* part4;
   int part_batch;
+  int part_tiles;    // tiles of the part4 layout (ntiles for G = 1, cg_tiles(nvox) for G > 1)
   int k;             // iteration index of this launch
   double* rho_hist;
   int hist_len;
   double tol;
+};
+
+// Device vectors of one 2D CG problem (single plan or serving slot).
+struct CgVectors {
+  c32* x;
+  c32* r[2];  // r[k & 1] is the input of launch k
+  c32* p[2];
+  c32* q;
+  c32* qpart;  // [G][B][nvox] when G > 1
+  int ngroups;
 };
 
 // Supported transform lengths (compile-time instantiations).
@@ -115,16 +141,32 @@ int ehe_tile_width(long ny);
 // Tiles of the CG vector kernels per batch element.
 int cg_tiles(long nvox);
 
+// Coil groups: with fewer than kFillBlocks (tiles x batch) blocks the fused
+// kernel splits the coils into G = ceil(kFillBlocks / blocks) groups, at
+// most ncoils / 2 (two coils per group) and kMaxCoilGroups.  Measured on
+// MI355X: a split pays off below about 512 blocks (256^2 x 16 coils, one
+// slice: 50.7 us unsplit, 22.9 us at G = 8; 384^2 x 32 coils x 8 slices:
+// 194 us unsplit, 142 us at G = 2) and costs above it (160 slices of 256^2:
+// 266 us unsplit, 354 us at G = 2).
+#ifndef SENSE_FILL_BLOCKS
+#define SENSE_FILL_BLOCKS 512
+#endif
+constexpr int kFillBlocks = SENSE_FILL_BLOCKS;
+constexpr int kMaxCoilGroups = 16;
+// Automatic coil-group count of a 2D plan (1 for 3D).
+int auto_coil_groups(long nx, long ny, int ncoils, int batch);
+
 // Launchers; return hipSuccess or the launch error.
+// q = E^H E p + lambda p; qpart is the [G][B][nvox] scratch when ngroups > 1.
 hipError_t launch_ehe(const Geom& g, const Tables& tb, const void* maps, const c32* p, c32* q,
-                      float lambda, double* eta_part, hipStream_t st);
+                      float lambda, double* eta_part, c32* qpart, int ngroups, hipStream_t st);
 // Fused CG iteration k (2D): finishes iteration k-1 (x, r, p updates) and
-// computes q = A p with the partials of the next scalars.
-hipError_t launch_ehe_cg(const Geom& g, const Tables& tb, const void* maps, c32* x, c32* r, c32* p,
-                         c32* q, float lambda, int k, const CgArgs& cg, hipStream_t st);
+// computes q = A p with the partials of the next scalars (with G > 1: the
+// group launch and its combine pass).
+hipError_t launch_ehe_cg(const Geom& g, const Tables& tb, const void* maps, const CgVectors& v,
+                         float lambda, int k, const CgArgs& cg, hipStream_t st);
 // After K fused iterations: x, r updates of iteration K-1 and <r, r>.
-hipError_t launch_cg_fused_final(const Geom& g, c32* x, c32* r, const c32* p, const c32* q, int K,
-                                 const CgArgs& cg, hipStream_t st);
+hipError_t launch_cg_fused_final(const Geom& g, const CgVectors& v, int K, const CgArgs& cg, hipStream_t st);
 // x = 0, r = p = b, q = 0 (q may be null), the <r, r> partials and a fresh
 // CgState per batch element.
 hipError_t launch_cg_init(const Geom& g, const c32* b, c32* x, c32* r, c32* p, c32* q,
@@ -134,11 +176,16 @@ hipError_t launch_cg_update(const Geom& g, c32* x, c32* r, const c32* p, const c
 hipError_t launch_cg_finish(const Geom& g, const CgArgs& cg, CgInfo* info, CgInfo* info2, hipStream_t st);
 hipError_t launch_cg_pupdate(const Geom& g, const c32* r, c32* p, const CgArgs& cg, hipStream_t st);
 
-// Batched CG iteration over single-slice problems (serving engine).
-void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, c32* x, c32* r, c32* p, c32* q,
-                        float lambda, int k, const CgArgs& cg, EheParams* out);
+// Batched CG iteration over single-slice problems (serving engine): one
+// group launch over the table rows (grid z = the largest G), then one
+// combine launch (rows with G = 1 skip it).
+void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, const CgVectors& v, float lambda,
+                        int k, const CgArgs& cg, EheParams* out);
 hipError_t launch_ehe_table(long ny, int maps_storage, const EheParams* d_table, int nproblems, int max_tiles,
-                            hipStream_t st);
+                            int max_groups, hipStream_t st);
+hipError_t launch_combine_table(const EheParams* d_table, int nproblems, int max_tiles, hipStream_t st);
+// Combine pass of one launch (plan path).
+hipError_t launch_combine(const EheParams& P, int batch, bool cg, hipStream_t st);
 
 
 // Full-grid forward and adjoint operators (2D).

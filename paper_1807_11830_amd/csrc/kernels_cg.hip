@@ -214,11 +214,90 @@ __global__ void __launch_bounds__(CG_NT) cg_fused_final_kernel(c32* __restrict__
   if (threadIdx.x == 0) cg.rr_part[(long)b * cg.rr_tiles + blockIdx.x] = tot;
 }
 
-hipError_t launch_cg_fused_final(const Geom& g, c32* x, c32* r, const c32* p, const c32* q, int K,
-                                 const CgArgs& cg, hipStream_t st) {
+hipError_t launch_cg_fused_final(const Geom& g, const CgVectors& v, int K, const CgArgs& cg, hipStream_t st) {
   const long nvox = g.nx * g.ny * g.nz;
   dim3 grid((unsigned)cg_tiles(nvox), (unsigned)g.batch);
-  hipLaunchKernelGGL(cg_fused_final_kernel, grid, dim3(CG_NT), 0, st, x, r, p, q, nvox, K, cg);
+  // launch K-1 left p_(K-1) and r_(K-1) in buffers K & 1
+  hipLaunchKernelGGL(cg_fused_final_kernel, grid, dim3(CG_NT), 0, st, v.x, v.r[K & 1], v.p[K & 1], v.q, nvox,
+                     K, cg);
+  return hipGetLastError();
+}
+
+// Coil-group combine of one problem row: q = sum_g qpart[g] + lambda p, the
+// groups added in index order.  CG mode (P.state set) also emits the fp64
+// partials Re<p,q>, Re<r,q>, <q,q>, <r,r> of launch k into part4[k & 1]
+// (one entry per block of this kernel) and skips a problem that has stopped.
+__device__ __forceinline__ void combine_body(const EheParams& P, const int b, const int tile, const bool cg) {
+  __shared__ double red[CG_NT / 64];
+  if (cg && P.state[b].status != CG_RUNNING) return;
+  const long nvox = P.nvox;
+  const long base = (long)b * nvox + (long)tile * CG_CHUNK;
+  const long lim = (long)b * nvox + nvox;
+  if (base >= lim) return;
+  const c32* pk = cg ? P.p_out : P.p_in;
+  const float lam = P.lambda;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < CG_STEPS; ++s) {
+    const long i = base + ((long)s * CG_NT + threadIdx.x) * CG_VEC;
+    if (i < lim) {
+      c32x2 qs = *reinterpret_cast<const c32x2*>(P.qpart + i);
+      for (int gr = 1; gr < P.ngroups; ++gr) {
+        const c32x2 t = *reinterpret_cast<const c32x2*>(P.qpart + (long)gr * P.qpart_gstride + i);
+        qs.a.re += t.a.re;
+        qs.a.im += t.a.im;
+        qs.b.re += t.b.re;
+        qs.b.im += t.b.im;
+      }
+      const c32x2 pv = *reinterpret_cast<const c32x2*>(pk + i);
+      c32x2 qv;
+      qv.a = {qs.a.re + lam * pv.a.re, qs.a.im + lam * pv.a.im};
+      qv.b = {qs.b.re + lam * pv.b.re, qs.b.im + lam * pv.b.im};
+      *reinterpret_cast<c32x2*>(P.q + i) = qv;
+      if (cg) {
+        const c32x2 rv = *reinterpret_cast<const c32x2*>(P.r_out + i);
+        acc[0] += (double)pv.a.re * qv.a.re + (double)pv.a.im * qv.a.im + (double)pv.b.re * qv.b.re +
+                  (double)pv.b.im * qv.b.im;
+        acc[1] += (double)rv.a.re * qv.a.re + (double)rv.a.im * qv.a.im + (double)rv.b.re * qv.b.re +
+                  (double)rv.b.im * qv.b.im;
+        acc[2] += (double)qv.a.re * qv.a.re + (double)qv.a.im * qv.a.im + (double)qv.b.re * qv.b.re +
+                  (double)qv.b.im * qv.b.im;
+        acc[3] += (double)rv.a.re * rv.a.re + (double)rv.a.im * rv.a.im + (double)rv.b.re * rv.b.re +
+                  (double)rv.b.im * rv.b.im;
+      }
+    }
+  }
+  if (!cg) return;
+  double* out = P.part4 + (((long)(P.k & 1) * P.part_batch + b) * P.part_tiles + tile) * 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double tot = block_sum<CG_NT>(acc[i], red);
+    if (threadIdx.x == 0) out[i] = tot;
+    __syncthreads();  // red is reused
+  }
+}
+
+template <bool CG>
+__global__ void __launch_bounds__(CG_NT) combine_kernel(EheParams P) {
+  combine_body(P, blockIdx.y, blockIdx.x, CG);
+}
+
+__global__ void __launch_bounds__(CG_NT) combine_table_kernel(const EheParams* __restrict__ table) {
+  const EheParams& P = table[blockIdx.y];
+  if (P.ngroups < 2) return;
+  combine_body(P, 0, blockIdx.x, true);
+}
+
+hipError_t launch_combine(const EheParams& P, int batch, bool cg, hipStream_t st) {
+  dim3 grid((unsigned)cg_tiles(P.nvox), (unsigned)batch);
+  if (cg) hipLaunchKernelGGL(combine_kernel<true>, grid, dim3(CG_NT), 0, st, P);
+  else hipLaunchKernelGGL(combine_kernel<false>, grid, dim3(CG_NT), 0, st, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine_table(const EheParams* d_table, int nproblems, int max_tiles, hipStream_t st) {
+  hipLaunchKernelGGL(combine_table_kernel, dim3((unsigned)max_tiles, (unsigned)nproblems), dim3(CG_NT), 0, st,
+                     d_table);
   return hipGetLastError();
 }
 

@@ -13,10 +13,12 @@
 // (Eq. (1)) around a masked forward/inverse transform pair.
 //
 // One block owns TX adjacent columns of one batch element (coalesced rows of
-// TX complex values) and loops over the coils; p, the coil's S column
-// segment and the accumulator q stay in registers, and the forward/inverse
-// transforms exchange through LDS only between Stockham stages.  The block
-// also emits its fp64 partial of Re<p, q> for CG.
+// TX complex values) and loops over the coils of its coil group; p, the
+// coil's S column segment and the accumulator q stay in registers, and the
+// forward/inverse transforms exchange through LDS only between Stockham
+// stages.  With one group the block also emits the fp64 partials of the CG
+// scalars; with several, each group writes its partial coil sum and a
+// combine pass adds them in group order.
 #include "bufio.hpp"
 #include "cg_scalar.hpp"
 #include "kernels.hpp"
@@ -27,7 +29,7 @@ namespace sense {
 
 
 template <int N, int ST, bool CG>
-__device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, const int b) {
+__device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, const int b, const int grp) {
   constexpr int T = EheLen<N>::T;
   constexpr int E = EheLen<N>::E;
   constexpr int TX = EheLen<N>::TX;
@@ -54,8 +56,8 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   // CG: the start-of-iteration scalars (every block derives the same ones)
   [[maybe_unused]] CgFused cgs{};
   if constexpr (CG) {
-    if (!cg_fused_begin(P.state + b, P.rr_part, P.rr_tiles, P.part4, P.part_batch, P.ntiles, P.rho_hist,
-                        P.hist_len, P.tol, P.k, b, tile == 0 && tid == 0, cgs))
+    if (!cg_fused_begin(P.state + b, P.rr_part, P.rr_tiles, P.part4, P.part_batch, P.part_tiles, P.rho_hist,
+                        P.hist_len, P.tol, P.k, b, tile == 0 && grp == 0 && tid == 0, cgs))
       return;
   }
 
@@ -92,9 +94,14 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   } else {
     // iteration k > 0 first finishes iteration k-1:
     //   x += alpha p,  r -= alpha q,  p = r + beta p
-    const Buf bp = make_buf(P.p_out + (long)b * nvox, img_bytes);
+    // Every coil group computes the new p for its own transforms; group 0
+    // stores x, r, p.
+    const Buf bp = make_buf(P.p_in + (long)b * nvox, img_bytes);
     const Buf br = make_buf(P.r + (long)b * nvox, img_bytes);
     const Buf bx = make_buf(P.x + (long)b * nvox, img_bytes);
+    const Buf bpo = make_buf(P.p_out + (long)b * nvox, img_bytes);
+    const Buf bro = make_buf(P.r_out + (long)b * nvox, img_bytes);
+    const bool owner = grp == 0;
     // Groups of G rows in a two-slot software pipeline: the loads of group
     // g+1 are issued before group g is updated and stored, so a wait for
     // group g never includes the stores of the group before it, and at most
@@ -117,7 +124,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
         lp[slot][i] = buf_load_c64(bp, lo, so);
         lr[slot][i] = buf_load_c64(br, lo, so);
         lq[slot][i] = buf_load_c64(bq, lo, so);
-        lx[slot][i] = buf_load_c64(bx, lo, so);
+        if (owner) lx[slot][i] = buf_load_c64(bx, lo, so);
       });
     };
     auto update_group = [&](auto gc, int slot) {
@@ -130,10 +137,10 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
         const c32 xv = {(float)((double)xv0.re + a * pv0.re), (float)((double)xv0.im + a * pv0.im)};
         const c32 rv = {(float)((double)lr[slot][i].re - a * qv.re), (float)((double)lr[slot][i].im - a * qv.im)};
         const c32 pv = {(float)((double)rv.re + bt * pv0.re), (float)((double)rv.im + bt * pv0.im)};
-        if (valid) {
+        if (valid && owner) {
           buf_store_c64(bx, xv, lo, so);
-          buf_store_c64(br, rv, lo, so);
-          buf_store_c64(bp, pv, lo, so);
+          buf_store_c64(bro, rv, lo, so);
+          buf_store_c64(bpo, pv, lo, so);
         }
         p[j] = pv;
         if constexpr (RREG) r[j] = rv;
@@ -194,25 +201,35 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
 #ifndef SENSE_EHE_PREFETCH
 #define SENSE_EHE_PREFETCH 0
 #endif
-  const int C = P.ncoils;
+  const int c0 = (int)((long)grp * P.ncoils / P.ngroups);
+  const int c1 = (int)((long)(grp + 1) * P.ncoils / P.ngroups);
 #if SENSE_EHE_PREFETCH
   // Maps of coil c+1 are loaded while coil c is transformed.
   c32 sc[E], sn[E];
-  load_s(sc, 0);
-  for (int c = 0; c < C; ++c) {
-    if (c + 1 < C) load_s(sn, c + 1);
+  load_s(sc, c0);
+  for (int c = c0; c < c1; ++c) {
+    if (c + 1 < c1) load_s(sn, c + 1);
     coil(sc);
 #pragma unroll
     for (int j = 0; j < E; ++j) sc[j] = sn[j];
   }
 #else
-  for (int c = 0; c < C; ++c) {
+  for (int c = c0; c < c1; ++c) {
     c32 sc[E];
     load_s(sc, c);
     coil(sc);
   }
 #endif
 
+  if (P.ngroups > 1) {
+    // partial coil sum of this group; the combine pass does the rest
+    const Buf bg = make_buf(P.qpart + (long)grp * P.qpart_gstride + (long)b * nvox, img_bytes);
+    if (valid) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) buf_store_c64(bg, q[j], voff * 8u, (uint32_t)j * rstep * 8u);
+    }
+    return;
+  }
   if constexpr (!CG) {
     double eta = 0.0;
 #pragma unroll
@@ -235,7 +252,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     // first q store, so no wait covers a store)
     c32 rr[RREG ? 1 : E];
     if constexpr (!RREG) {
-      const Buf brr = make_buf(P.r + (long)b * nvox, img_bytes);
+      const Buf brr = make_buf(P.r_out + (long)b * nvox, img_bytes);
 #pragma unroll
       for (int j = 0; j < E; ++j) rr[j] = buf_load_c64(brr, voff * 8u, (uint32_t)j * rstep * 8u);
       asm volatile("" ::: "memory");
@@ -254,7 +271,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
         if constexpr (RREG) acc[3] += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
       }
     }
-    double* out = P.part4 + (((long)(P.k & 1) * P.part_batch + b) * P.ntiles + tile) * 4;
+    double* out = P.part4 + (((long)(P.k & 1) * P.part_batch + b) * P.part_tiles + tile) * 4;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const double tot = block_sum<NT>(acc[i], red);
@@ -266,7 +283,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
 
 template <int N, int ST, bool CG>
 __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX) ehe2d_kernel(EheParams P) {
-  ehe2d_body<N, ST, CG>(P, blockIdx.x, blockIdx.y);
+  ehe2d_body<N, ST, CG>(P, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Batched CG launch over many independent single-slice problems of the same
@@ -277,8 +294,8 @@ template <int N, int ST>
 __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX)
     ehe2d_table_kernel(const EheParams* __restrict__ table) {
   const EheParams P = table[blockIdx.y];
-  if ((long)blockIdx.x >= (long)P.ntiles) return;
-  ehe2d_body<N, ST, true>(P, blockIdx.x, 0);
+  if ((long)blockIdx.x >= (long)P.ntiles || (int)blockIdx.z >= P.ngroups) return;
+  ehe2d_body<N, ST, true>(P, blockIdx.x, 0, blockIdx.z);
 }
 
 int ehe_tile_width(long ny) {
@@ -290,20 +307,36 @@ int ehe_tile_width(long ny) {
   return tx;
 }
 
-template <bool CG>
-static hipError_t launch_ehe_impl(const Geom& g, const Tables& tb, EheParams P, hipStream_t st) {
-  hipError_t err = hipErrorInvalidValue;
+int auto_coil_groups(long nx, long ny, int ncoils, int batch) {
+  const int tx = ehe_tile_width(ny);
+  if (tx == 0) return 1;
+  const long blocks = (nx + tx - 1) / tx * (long)batch;
+  if (blocks >= kFillBlocks) return 1;
+  long gr = (kFillBlocks + blocks - 1) / blocks;
+  if (gr > ncoils / 2) gr = ncoils / 2;
+  if (gr > kMaxCoilGroups) gr = kMaxCoilGroups;
+  return (int)(gr < 1 ? 1 : gr);
+}
+
+static void fill_common(const Geom& g, const Tables& tb, EheParams& P) {
   P.tw = tb.tw_y;
   P.mu = tb.mu_y;
   P.nx = g.nx;
+  P.nvox = g.nx * g.ny;
   P.ntiles = (int)((g.nx + ehe_tile_width(g.ny) - 1) / ehe_tile_width(g.ny));
   P.maps_bstride = g.maps_bstride;
   P.ncoils = g.ncoils;
+  P.qpart_gstride = (long)g.batch * P.nvox;
+}
+
+template <bool CG>
+static hipError_t launch_ehe_impl(const Geom& g, const EheParams& P, hipStream_t st) {
+  hipError_t err = hipErrorInvalidValue;
   dispatch_length(g.ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     constexpr int T = EheLen<N>::T;
     constexpr int TX = EheLen<N>::TX;
-    dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)g.batch);
+    dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)g.batch, (unsigned)P.ngroups);
     dim3 block(T * TX);
     switch (g.maps_storage) {
       case ST_C64: hipLaunchKernelGGL((ehe2d_kernel<N, ST_C64, CG>), grid, block, 0, st, P); break;
@@ -316,41 +349,40 @@ static hipError_t launch_ehe_impl(const Geom& g, const Tables& tb, EheParams P, 
   return err;
 }
 
-void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, c32* x, c32* r, c32* p, c32* q,
-                        float lambda, int k, const CgArgs& cg, EheParams* out) {
+void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, const CgVectors& v, float lambda,
+                        int k, const CgArgs& cg, EheParams* out) {
   EheParams P{};
+  fill_common(g, tb, P);
   P.maps = maps;
-  P.x = x;
-  P.r = r;
+  P.x = v.x;
+  P.r = v.r[k & 1];
+  P.r_out = v.r[(k + 1) & 1];
+  P.p_in = v.p[k & 1];
+  P.p_out = v.p[(k + 1) & 1];
+  P.q = v.q;
+  P.qpart = v.qpart;
+  P.ngroups = v.ngroups;
   P.k = k;
-  P.part4 = cg.part4;
-  P.part_batch = cg.part_batch;
-  P.p_in = p;
-  P.p_out = p;
-  P.q = q;
   P.lambda = lambda;
   P.eta_part = cg.eta_part;
   P.state = cg.state;
   P.rr_part = cg.rr_part;
   P.rr_tiles = cg.rr_tiles;
+  P.part4 = cg.part4;
+  P.part_batch = cg.part_batch;
+  P.part_tiles = cg.part_tiles;
   P.rho_hist = cg.rho_hist;
   P.hist_len = cg.hist_len;
   P.tol = cg.tol;
-  P.tw = tb.tw_y;
-  P.mu = tb.mu_y;
-  P.nx = g.nx;
-  P.ntiles = (int)((g.nx + ehe_tile_width(g.ny) - 1) / ehe_tile_width(g.ny));
-  P.maps_bstride = g.maps_bstride;
-  P.ncoils = g.ncoils;
   *out = P;
 }
 
 hipError_t launch_ehe_table(long ny, int maps_storage, const EheParams* d_table, int nproblems, int max_tiles,
-                            hipStream_t st) {
+                            int max_groups, hipStream_t st) {
   hipError_t err = hipErrorInvalidValue;
   dispatch_length(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    dim3 grid((unsigned)max_tiles, (unsigned)nproblems);
+    dim3 grid((unsigned)max_tiles, (unsigned)nproblems, (unsigned)max_groups);
     dim3 block(EheLen<N>::T * EheLen<N>::TX);
     switch (maps_storage) {
       case ST_C64: hipLaunchKernelGGL((ehe2d_table_kernel<N, ST_C64>), grid, block, 0, st, d_table); break;
@@ -364,21 +396,28 @@ hipError_t launch_ehe_table(long ny, int maps_storage, const EheParams* d_table,
 }
 
 hipError_t launch_ehe(const Geom& g, const Tables& tb, const void* maps, const c32* p, c32* q,
-                      float lambda, double* eta_part, hipStream_t st) {
+                      float lambda, double* eta_part, c32* qpart, int ngroups, hipStream_t st) {
   EheParams P{};
+  fill_common(g, tb, P);
   P.maps = maps;
   P.p_in = p;
   P.q = q;
+  P.qpart = qpart;
+  P.ngroups = ngroups;
   P.lambda = lambda;
   P.eta_part = eta_part;
-  return launch_ehe_impl<false>(g, tb, P, st);
+  hipError_t e = launch_ehe_impl<false>(g, P, st);
+  if (e == hipSuccess && ngroups > 1) e = launch_combine(P, g.batch, false, st);
+  return e;
 }
 
-hipError_t launch_ehe_cg(const Geom& g, const Tables& tb, const void* maps, c32* x, c32* r, c32* p,
-                         c32* q, float lambda, int k, const CgArgs& cg, hipStream_t st) {
+hipError_t launch_ehe_cg(const Geom& g, const Tables& tb, const void* maps, const CgVectors& v,
+                         float lambda, int k, const CgArgs& cg, hipStream_t st) {
   EheParams P{};
-  fill_ehe_cg_params(g, tb, maps, x, r, p, q, lambda, k, cg, &P);
-  return launch_ehe_impl<true>(g, tb, P, st);
+  fill_ehe_cg_params(g, tb, maps, v, lambda, k, cg, &P);
+  hipError_t e = launch_ehe_impl<true>(g, P, st);
+  if (e == hipSuccess && v.ngroups > 1) e = launch_combine(P, g.batch, true, st);
+  return e;
 }
 
 }  // namespace sense

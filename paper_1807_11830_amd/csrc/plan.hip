@@ -6,6 +6,7 @@
 // model (its FFT process bakes the transform plan in init() because that
 // takes far longer than a transform); every apply call afterwards only
 // enqueues kernels on the caller's stream and never allocates.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -48,6 +49,7 @@ static Layout make_layout(const sense_desc& d) {
     L.eta_tiles = (int)((d.nx + tx - 1) / tx);
   }
   L.rr_tiles = cg_tiles((long)nvox);
+  L.ngroups = d.ndim == 2 ? auto_coil_groups(d.nx, d.ny, d.ncoils, d.batch) : 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -65,10 +67,15 @@ static Layout make_layout(const sense_desc& d) {
   L.r = take(sizeof(c32) * B * nvox);
   L.p = take(sizeof(c32) * B * nvox);
   L.q = take(sizeof(c32) * B * nvox);
+  // 2D CG double-buffers r and p; coil groups need [G][B][nvox] partials
+  L.r2 = d.ndim == 2 ? take(sizeof(c32) * B * nvox) : L.r;
+  L.p2 = d.ndim == 2 ? take(sizeof(c32) * B * nvox) : L.p;
+  L.qpart = L.ngroups > 1 ? take(sizeof(c32) * (size_t)L.ngroups * B * nvox) : 0;
   L.state = take(sizeof(CgState) * B);
   L.eta_part = take(sizeof(double) * B * (size_t)L.eta_tiles);
   L.rr_part = take(sizeof(double) * B * (size_t)L.rr_tiles);
-  L.part4 = take(sizeof(double) * 2 * B * (size_t)L.eta_tiles * 4);
+  const size_t ptiles = (size_t)std::max(L.eta_tiles, L.rr_tiles);
+  L.part4 = take(sizeof(double) * 2 * B * ptiles * 4);
   L.info = take(sizeof(CgInfo) * B);
   L.total = off;
   return L;
@@ -158,8 +165,9 @@ hipError_t enqueue_iteration(sense_plan p, c32* x, float lambda, int k, const Cg
     if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
     if (e == hipSuccess) e = launch_cg_update(p->g, x, r, pv, q, cg, st);
   } else {
-    // one launch: the updates of iteration k-1 fused in front of q = A p
-    e = launch_ehe_cg(p->g, p->tb, p->maps, x, r, pv, q, lambda, k, cg, st);
+    // one launch (plus the combine pass with coil groups): the updates of
+    // iteration k-1 fused in front of q = A p
+    e = launch_ehe_cg(p->g, p->tb, p->maps, p->vectors(x), lambda, k, cg, st);
     if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
   }
   return e;
@@ -167,8 +175,7 @@ hipError_t enqueue_iteration(sense_plan p, c32* x, float lambda, int k, const Cg
 
 hipError_t enqueue_solve_end(sense_plan p, c32* x, int K, const CgArgs& cg, CgInfo* d_info, hipStream_t st) {
   hipError_t e = hipSuccess;
-  if (p->d.ndim != 3 && K > 0)
-    e = launch_cg_fused_final(p->g, x, p->at<c32>(p->L.r), p->at<c32>(p->L.p), p->at<c32>(p->L.q), K, cg, st);
+  if (p->d.ndim != 3 && K > 0) e = launch_cg_fused_final(p->g, p->vectors(x), K, cg, st);
   if (e == hipSuccess) e = launch_cg_finish(p->g, cg, p->at<CgInfo>(p->L.info), d_info, st);
   return e;
 }
@@ -232,6 +239,7 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
       return fail(SENSE_ERR_DEVICE, "hipGetDevice failed");
     }
     p->L = make_layout(d);
+    p->ngroups = p->L.ngroups;
     const size_t nvox = (size_t)d.nx * d.ny * d.nz;
     p->g.nx = d.nx;
     p->g.ny = d.ny;
@@ -365,7 +373,7 @@ sense_status sense_apply_EHE(sense_plan p, const void* d_p, void* d_q, double la
                                            static_cast<c32*>(d_q), p->at<c32>(p->L.work), (float)lambda,
                                            p->at<double>(p->L.eta_part), st)
                      : launch_ehe(p->g, p->tb, p->maps, static_cast<const c32*>(d_p), static_cast<c32*>(d_q),
-                                  (float)lambda, p->at<double>(p->L.eta_part), st);
+                                  (float)lambda, nullptr, p->at<c32>(p->L.qpart), p->ngroups, st);
   if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
   return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_apply_EHE launch");
 }
@@ -425,6 +433,29 @@ sense_status sense_plan_set_maps(sense_plan p, const void* d_maps) {
     (void)hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
   }
+  return SENSE_OK;
+}
+
+sense_status sense_plan_set_coil_groups(sense_plan p, int32_t groups) {
+  if (!p) return fail(SENSE_ERR_INVALID, "plan is NULL");
+  if (p->busy) return fail(SENSE_ERR_STATE, "plan is in a serving-engine slot");
+  if (groups < 0) return fail(SENSE_ERR_INVALID, "groups must be >= 0");
+  if (groups > p->L.ngroups)
+    return fail(SENSE_ERR_UNSUPPORTED, "at most " + std::to_string(p->L.ngroups) +
+                                           " coil groups fit this plan's workspace");
+  const int g = groups == 0 ? p->L.ngroups : groups;
+  if (g != p->ngroups && p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  p->ngroups = g;
+  return SENSE_OK;
+}
+
+sense_status sense_plan_coil_groups(sense_plan p, int32_t* groups, int32_t* max_groups) {
+  if (!p) return fail(SENSE_ERR_INVALID, "plan is NULL");
+  if (groups) *groups = p->ngroups;
+  if (max_groups) *max_groups = p->L.ngroups;
   return SENSE_OK;
 }
 

@@ -13,10 +13,11 @@ namespace sense {
 
 struct Layout {
   size_t tw_x, tw_y, tw_z, mu_y, mask_c, rows_s, rows_u;
-  size_t work, r, p, q;
+  size_t work, r, p, q, r2, p2, qpart;
   size_t state, eta_part, rr_part, part4, info;
   size_t total;
   int eta_tiles, rr_tiles;
+  int ngroups;  // coil groups the workspace holds (the automatic choice)
 };
 
 sense_status fail(sense_status s, const std::string& msg);
@@ -44,6 +45,7 @@ struct sense_plan_s {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used;
   bool busy;  // owned by a serving-engine slot
+  int ngroups;  // coil groups of the 2D normal operator (1 .. L.ngroups)
   // whole-solve graph, replayed while the solve arguments repeat
   bool graphs;
   hipStream_t cap_stream;
@@ -65,6 +67,18 @@ struct sense_plan_s {
   T* at(size_t off) const {
     return reinterpret_cast<T*>(mem + off);
   }
+  sense::CgVectors vectors(sense::c32* x) const {
+    sense::CgVectors v{};
+    v.x = x;
+    v.r[0] = at<sense::c32>(L.r);
+    v.r[1] = at<sense::c32>(L.r2);
+    v.p[0] = at<sense::c32>(L.p);
+    v.p[1] = at<sense::c32>(L.p2);
+    v.q = at<sense::c32>(L.q);
+    v.qpart = ngroups > 1 ? at<sense::c32>(L.qpart) : nullptr;
+    v.ngroups = ngroups;
+    return v;
+  }
   CgArgs cg_args(double tol, double* hist, int hist_len) const {
     CgArgs a{};
     a.state = at<sense::CgState>(L.state);
@@ -73,7 +87,7 @@ struct sense_plan_s {
     a.eta_tiles = L.eta_tiles;
     a.rr_tiles = L.rr_tiles;
     a.part4 = at<double>(L.part4);
-    a.part_tiles = L.eta_tiles;
+    a.part_tiles = ngroups > 1 ? L.rr_tiles : L.eta_tiles;
     a.part_batch = d.batch;
     a.rho_hist = hist;
     a.hist_len = hist_len;

@@ -54,7 +54,8 @@ class CgInfo(ctypes.Structure):
 ABI_FUNCTIONS = ("sense_plan_device_bytes", "sense_plan_create", "sense_plan_destroy",
                  "sense_apply_E", "sense_apply_EH", "sense_apply_EHE", "sense_cg_solve",
                  "sense_plan_cg_info", "sense_plan_set_profiling", "sense_plan_profile",
-                 "sense_plan_set_graphs", "sense_plan_set_maps", "sense_engine_create", "sense_engine_destroy",
+                 "sense_plan_set_graphs", "sense_plan_set_maps", "sense_plan_set_coil_groups",
+                 "sense_plan_coil_groups", "sense_engine_create", "sense_engine_destroy",
                  "sense_engine_admit", "sense_engine_step", "sense_engine_poll", "sense_engine_stats",
                  "sense_engine_sync", "sense_last_error", "sense_version")
 
@@ -83,6 +84,8 @@ def lib():
     L.sense_plan_set_profiling.argtypes = [P, I32]
     L.sense_plan_set_graphs.argtypes = [P, I32]
     L.sense_plan_set_maps.argtypes = [P, P]
+    L.sense_plan_set_coil_groups.argtypes = [P, I32]
+    L.sense_plan_coil_groups.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     L.sense_plan_profile.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(D)]
     L.sense_engine_create.argtypes = [ctypes.c_size_t, I32, ctypes.POINTER(P)]
     L.sense_engine_destroy.argtypes = [P]
@@ -318,6 +321,16 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(lib().sense_plan_set_maps(self._h, _ptr(m)))
         self._maps = m
+
+    def set_coil_groups(self, groups: int):
+        """Force G coil groups (1 = no split; 0 = the plan's automatic choice)."""
+        _check(lib().sense_plan_set_coil_groups(self._h, int(groups)))
+
+    def coil_groups(self):
+        """(current G, largest G the plan's workspace holds)."""
+        g, gm = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().sense_plan_coil_groups(self._h, ctypes.byref(g), ctypes.byref(gm)))
+        return g.value, gm.value
 
     def set_graphs(self, on: bool):
         """Replay whole solves from a captured HIP graph (default on)."""

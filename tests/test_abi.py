@@ -54,8 +54,16 @@ def test_device_bytes():
     d = _desc(nx=256, ny=256, ncoils=12, batch=3)
     nb = L.sense_plan_device_bytes(ctypes.byref(d))
     nvox = 256 * 256
-    assert nb >= 8 * nvox * 3 * (12 + 3)  # workspace + r, p, q
-    assert nb < 8 * nvox * 3 * (12 + 3) + (1 << 20)
+    # 16 column tiles x 3 slices = 48 blocks < 512: the plan splits the 12
+    # coils into min(ceil(512 / 48), 12 / 2, 16) = 6 groups
+    G = 6
+    # workspace + r, p, q and the second r, p + the group partials
+    vecs = 8 * nvox * 3 * (12 + 5 + G)
+    assert vecs <= nb < vecs + (1 << 20)
+    d = _desc(nx=256, ny=256, ncoils=12, batch=32)  # 512 blocks: no split
+    nb = L.sense_plan_device_bytes(ctypes.byref(d))
+    vecs = 8 * nvox * 32 * (12 + 5)
+    assert vecs <= nb < vecs + (1 << 20)
     for bad in (dict(ndim=4), dict(nx=0), dict(ny=100), dict(nz=2), dict(ncoils=0),
                 dict(maps_storage=7), dict(ndim=3, nz=7)):
         assert L.sense_plan_device_bytes(ctypes.byref(_desc(**bad))) == 0, bad
@@ -100,7 +108,9 @@ def test_null_arguments():
                     ("sense_apply_EHE", (None, None, None, 0.0, None)),
                     ("sense_cg_solve", (None, None, None, 1, 0.0, 0.0, None, None, None)),
                     ("sense_plan_destroy", (None,)),
-                    ("sense_plan_set_profiling", (None, 1))):
+                    ("sense_plan_set_profiling", (None, 1)),
+                    ("sense_plan_set_coil_groups", (None, 1)),
+                    ("sense_plan_coil_groups", (None, None, None))):
         assert getattr(L, f)(*args) == 1, f
         assert "plan is NULL" in L.sense_last_error().decode()
 

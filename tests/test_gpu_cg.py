@@ -65,6 +65,25 @@ def test_cg_slice256_matches_oracle(iters, tol):
     assert abs(fg[0] - fo[0]) <= 1e-6 * fo[0]
 
 
+@pytest.mark.parametrize("G", [1, 2])
+def test_cg_coil_groups(G):
+    """The 64x64 / 4-coil solve with the coils split into G groups (the
+    plan's own choice is 2) matches the oracle; the same G is bitwise
+    reproducible."""
+    w = synth.SMALL_64
+    imgs, maps, mask, y = _problem(w)
+    xo, it, st, hist = oracle.cg(y, maps, mask, w.iters)
+    with sense.Plan(to_dev(maps), mask, batch=1) as plan:
+        assert plan.coil_groups() == (2, 2)
+        plan.set_coil_groups(G)
+        r1 = plan.cg(to_dev(y), w.iters).x.clone()
+        r2 = plan.cg(to_dev(y), w.iters).x
+    err = rel_l2(to_host(r1), xo)
+    log(f"64x64 CG G={G} rel-L2 {err:.3e}")
+    assert err <= TOL_FP32
+    assert torch.equal(r1, r2)
+
+
 def test_cg_batch_per_slice_maps():
     w = synth.SMALL_64
     imgs, maps, mask, y = _problem(w, batch=3, per_slice_maps=True)

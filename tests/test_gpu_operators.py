@@ -37,6 +37,27 @@ def test_ehe_matches_oracle(ny, nx, nc, b, per):
     assert err <= TOL_FP32
 
 
+def test_ehe_coil_groups():
+    """5 column tiles x 2 slices fill few blocks, so the plan splits the 7
+    coils into 3 groups (2, 2 and 3 coils); a forced smaller, uneven split
+    and no split give the same operator to the fp32 bar."""
+    maps, x, mask = rand_case(128, 72, 7, 2, True, seed=9)
+    ref = oracle.A(x, maps, mask, lam=0.2)
+    with sense.Plan(to_dev(maps), mask, batch=2) as plan:
+        g, gmax = plan.coil_groups()
+        assert g == gmax == 3
+        for G in (1, 2, 3):
+            plan.set_coil_groups(G)
+            q = to_host(plan.EHE(to_dev(x), lam=0.2))
+            err = rel_l2(q, ref)
+            log(f"  G={G} rel-L2 {err:.3e}")
+            assert err <= TOL_FP32
+        with pytest.raises(sense.SenseError, match="coil groups"):
+            plan.set_coil_groups(gmax + 1)
+        plan.set_coil_groups(0)
+        assert plan.coil_groups() == (gmax, gmax)
+
+
 def test_ehe_lambda():
     maps, x, mask = rand_case(128, 48, 3, 2, False, seed=5)
     ref = oracle.A(x, maps, mask, lam=0.37)
