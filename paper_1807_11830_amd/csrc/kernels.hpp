@@ -88,9 +88,10 @@ struct CgArgs {
 // adds the G partials in group order (deterministic), adds lambda p and
 // emits the partials of the scalars.  G = 1 does all of it in one launch.
 //
-// CG vectors r and p are double-buffered: launch k reads r_in, p_in
-// (iterate k-1) and writes r_out, p_out (iterate k), so blocks of other
-// coil groups never see a half-updated vector.
+// With coil groups the CG vectors r and p are double-buffered: launch k
+// reads r_in, p_in (iterate k-1) and writes r_out, p_out (iterate k), so
+// blocks of other groups never see a half-updated vector.  With one group
+// r_out = r_in and p_out = p_in (each block updates its own tile in place).
 struct EheParams {
   const void* maps;
   const c32* r;      // CG: r_(k-1) (input of the update); apply: unused
@@ -127,7 +128,7 @@ struct EheParams {
 // Device vectors of one 2D CG problem (single plan or serving slot).
 struct CgVectors {
   c32* x;
-  c32* r[2];  // r[k & 1] is the input of launch k
+  c32* r[2];  // r[k & 1] is the input of launch k (the same buffer twice for G = 1)
   c32* p[2];
   c32* q;
   c32* qpart;  // [G][B][nvox] when G > 1

@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
   constexpr int TR = ROW_NT / T;
   constexpr int LDL = N + 1;
   using Rad = typename Len<N>::R;
-  __shared__ c32 buf[2][TR * LDL];
+  __shared__ c32 buf[TR * LDL];
   __shared__ c32 tw[N];
 
   const int tid = threadIdx.x;
@@ -74,8 +74,8 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
 #pragma unroll
   for (int j = 0; j < E; ++j) v[j] = valid ? cscale(load_c<ST_IN>(in, t + T * j), sgn) : c32{0.f, 0.f};
   __syncthreads();
-  LineView<1> b0{&buf[0][l * LDL]}, b1{&buf[1][l * LDL]};
-  fft_line<N, T, DIR, 0>(v, t, TwTable{tw}, b0, b1, Rad{});
+  LineView<1> lv{&buf[l * LDL]};
+  fft_line_sb<N, T, DIR>(v, t, TwTable{tw}, lv, Rad{});
   if (valid) {
     TO* out = static_cast<TO*>(P.out) + off;
     const float s = sgn * P.scale;
@@ -125,11 +125,23 @@ struct ColPass {
   float lambda;
 };
 
+// Columns per block of a pass along AXIS.  Along z consecutive rows of a
+// column are a whole x-y plane apart, so each row segment is its own DRAM
+// page: wider segments (32 columns, 256 bytes) where the block stays within
+// 256 threads.
+#ifndef SENSE_ZTX
+#define SENSE_ZTX 32
+#endif
+template <int T, int AXIS>
+constexpr int pass_tile() {
+  return (AXIS == 2 && T * SENSE_ZTX <= 256) ? SENSE_ZTX : col_tile<T>();
+}
+
 template <int N, int AXIS, int MODE, int ST>
-__global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) colpass_kernel(ColPass P) {
+__global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) colpass_kernel(ColPass P) {
   constexpr int T = Len<N>::T;
   constexpr int E = Len<N>::E;
-  constexpr int TX = col_tile<T>();
+  constexpr int TX = pass_tile<T, AXIS>();
   constexpr int NT = T * TX;
   using Rad = typename Len<N>::R;
   __shared__ c32 buf[N * TX];
@@ -210,8 +222,13 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) colpass_ker
     c32 acc[E];
 #pragma unroll
     for (int j = 0; j < E; ++j) acc[j] = {0.f, 0.f};
+#ifndef SENSE_ADJ_SPRE
+#define SENSE_ADJ_SPRE 1
+#endif
     for (int c = 0; c < P.ncoils; ++c) {
       const Buf bw = make_buf(P.src + (b * P.ncoils + c) * nvox, vbytes);
+      const Buf bs = make_buf(static_cast<const SType*>(P.maps) + b * P.maps_bstride + (long)c * nvox,
+                              (uint32_t)(nvox * sizeof(SType)));
       c32 u[E];
 #pragma unroll
       for (int j = 0; j < E; ++j) {
@@ -220,13 +237,21 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) colpass_ker
         if (on) v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
         u[j] = cscale(v, sgn);
       }
+      // the coil's maps are loaded before the transform so their latency
+      // hides behind it (measured 16% faster for 256^2 x 12 coils x 160
+      // slices than loading them after it, at one wave less per SIMD)
+      [[maybe_unused]] c32 sv[SENSE_ADJ_SPRE ? E : 1];
+      if constexpr (SENSE_ADJ_SPRE != 0) {
+#pragma unroll
+        for (int j = 0; j < E; ++j) sv[j] = buf_load_st<ST>(bs, voff + (uint32_t)j * rstep, 0);
+      }
       fft_line_sb<N, T, +1>(u, t, twt, lv, Rad{});
-      const Buf bs = make_buf(static_cast<const SType*>(P.maps) + b * P.maps_bstride + (long)c * nvox,
-                              (uint32_t)(nvox * sizeof(SType)));
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        const c32 sv = buf_load_st<ST>(bs, voff + (uint32_t)j * rstep, 0);
-        acc[j] = cfma_conj(acc[j], sv, cscale(u[j], sgn));
+        c32 s;
+        if constexpr (SENSE_ADJ_SPRE != 0) s = sv[j];
+        else s = buf_load_st<ST>(bs, voff + (uint32_t)j * rstep, 0);
+        acc[j] = cfma_conj(acc[j], s, cscale(u[j], sgn));
       }
     }
     const Buf bd = make_buf(P.dst + b * nvox, vbytes);
@@ -309,7 +334,7 @@ static hipError_t launch_colpass(const Geom& g, ColPass P, long n, hipStream_t s
   P.ncoils = g.ncoils;
   dispatch_length(n, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    constexpr int TX = col_tile<Len<N>::T>();
+    constexpr int TX = pass_tile<Len<N>::T, AXIS>();
     const long planes = AXIS == 1 ? g.nz : g.ny;
     const long zdim = MODE == CM_ADJ_COIL ? g.batch : (long)g.batch * g.ncoils;
     dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)planes, (unsigned)zdim);

@@ -124,7 +124,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
         lp[slot][i] = buf_load_c64(bp, lo, so);
         lr[slot][i] = buf_load_c64(br, lo, so);
         lq[slot][i] = buf_load_c64(bq, lo, so);
-        if (owner) lx[slot][i] = buf_load_c64(bx, lo, so);
+        lx[slot][i] = buf_load_c64(bx, lo, so);  // unconditional: keeps the waits exact
       });
     };
     auto update_group = [&](auto gc, int slot) {

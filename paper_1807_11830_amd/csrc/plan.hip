@@ -67,9 +67,10 @@ static Layout make_layout(const sense_desc& d) {
   L.r = take(sizeof(c32) * B * nvox);
   L.p = take(sizeof(c32) * B * nvox);
   L.q = take(sizeof(c32) * B * nvox);
-  // 2D CG double-buffers r and p; coil groups need [G][B][nvox] partials
-  L.r2 = d.ndim == 2 ? take(sizeof(c32) * B * nvox) : L.r;
-  L.p2 = d.ndim == 2 ? take(sizeof(c32) * B * nvox) : L.p;
+  // with coil groups the 2D CG double-buffers r and p and keeps
+  // [G][B][nvox] partial coil sums
+  L.r2 = L.ngroups > 1 ? take(sizeof(c32) * B * nvox) : L.r;
+  L.p2 = L.ngroups > 1 ? take(sizeof(c32) * B * nvox) : L.p;
   L.qpart = L.ngroups > 1 ? take(sizeof(c32) * (size_t)L.ngroups * B * nvox) : 0;
   L.state = take(sizeof(CgState) * B);
   L.eta_part = take(sizeof(double) * B * (size_t)L.eta_tiles);

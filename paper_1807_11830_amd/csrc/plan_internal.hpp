@@ -70,10 +70,13 @@ struct sense_plan_s {
   sense::CgVectors vectors(sense::c32* x) const {
     sense::CgVectors v{};
     v.x = x;
+    // one group updates r and p in place (every block owns its tile);
+    // several groups read the previous iterate while group 0 writes the next
+    const bool pp = ngroups > 1;
     v.r[0] = at<sense::c32>(L.r);
-    v.r[1] = at<sense::c32>(L.r2);
+    v.r[1] = at<sense::c32>(pp ? L.r2 : L.r);
     v.p[0] = at<sense::c32>(L.p);
-    v.p[1] = at<sense::c32>(L.p2);
+    v.p[1] = at<sense::c32>(pp ? L.p2 : L.p);
     v.q = at<sense::c32>(L.q);
     v.qpart = ngroups > 1 ? at<sense::c32>(L.qpart) : nullptr;
     v.ngroups = ngroups;

@@ -62,7 +62,7 @@ def test_device_bytes():
     assert vecs <= nb < vecs + (1 << 20)
     d = _desc(nx=256, ny=256, ncoils=12, batch=32)  # 512 blocks: no split
     nb = L.sense_plan_device_bytes(ctypes.byref(d))
-    vecs = 8 * nvox * 32 * (12 + 5)
+    vecs = 8 * nvox * 32 * (12 + 3)
     assert vecs <= nb < vecs + (1 << 20)
     for bad in (dict(ndim=4), dict(nx=0), dict(ny=100), dict(nz=2), dict(ncoils=0),
                 dict(maps_storage=7), dict(ndim=3, nz=7)):
