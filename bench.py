@@ -70,7 +70,7 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--maps-storage", default="c64", choices=["c64", "bf16", "fp16"])
-    ap.add_argument("--workload", default="cgsense", choices=["cgsense", "serving", "precision", "autograd3d"],
+    ap.add_argument("--workload", default="cgsense", choices=["cgsense", "serving", "precision", "autograd3d", "paper"],
                     help="cgsense (default, the metric's workload); the others print their own line")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -130,7 +130,7 @@ def main():
               "(slices are independent: shard the batch across processes instead)", file=sys.stderr)
         sys.exit(2)
     {"cgsense": run_cgsense, "serving": run_serving, "precision": run_precision,
-     "autograd3d": run_autograd3d}[args.workload](args)
+     "autograd3d": run_autograd3d, "paper": run_paper}[args.workload](args)
 
 
 def run_serving(args):
@@ -244,6 +244,47 @@ def run_precision(args):
                       "value": out["bf16"]["applies_per_s"], "unit": "applies/s", "n_gpus": 1,
                       "higher_is_better": True, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": w.name, "slices": B, "iters": K}, "variants": out}), flush=True)
+
+
+def run_paper(args):
+    """The paper's reconstruction workload (Section "Performance comparison
+    with other frameworks"): 16 frames of 160x160 with 8 coils, fully sampled
+    Cartesian k-space; the Eq. (1) reconstruction (E^H at full sampling) and
+    the root-sum-of-squares reconstruction, each timed over 100 runs."""
+    import torch
+
+    from paper_1807_11830_amd import sense, synth
+
+    n, C, B, reps = 160, 8, 16, 100
+    dev = torch.device("cuda:0")
+    full = np.ones(n, np.uint8)
+    maps = torch.from_numpy(synth.coil_maps2d(n, C).astype(np.complex64)).to(dev)
+    imgs = torch.from_numpy(np.stack([synth.phantom2d(n, seed=synth.SEED_PHANTOM + f)
+                                      for f in range(B)]).astype(np.complex64)).to(dev)
+    out = {}
+    with sense.Plan(maps, full, batch=B) as plan:
+        y = plan.E(imgs)
+        x = torch.empty_like(imgs)
+        img = torch.empty((B, n, n), dtype=torch.float32, device=dev)
+        for name, f, nbytes in (("eq1_EH", lambda: plan.EH(y, out=x), 8 * n * n * (B * C + C + B)),
+                                ("rss", lambda: plan.rss(y, out=img), 8 * n * n * B * C + 4 * n * n * B)):
+            for _ in range(10):
+                f()
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for _ in range(reps):
+                f()
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / reps
+            out[name] = {"ms": ms, "algorithmic_bytes": nbytes, "achieved_gbs": nbytes / ms / 1e6}
+            log(f"paper: {name} {ms * 1e3:.1f} us per 16-frame reconstruction ({nbytes / ms / 1e6:.0f} GB/s)")
+    print(json.dumps({"metric": "reconstructions/s (16 frames 160x160, 8 coils, fully sampled)",
+                      "value": 1e3 / out["rss"]["ms"], "unit": "RSS reconstructions/s", "n_gpus": 1,
+                      "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "paper_16x160x160_c8_full", "frames": B, "coils": C},
+                      "results": out}), flush=True)
 
 
 def run_autograd3d(args):

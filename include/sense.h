@@ -152,6 +152,16 @@ SENSE_API sense_status sense_apply_E(sense_plan plan, const void* d_x, void* d_y
 SENSE_API sense_status sense_apply_EH(sense_plan plan, const void* d_y, void* d_x, void* stream);
 
 /*
+ * Root-sum-of-squares reconstruction (the paper's RSS, Section "Performance
+ * comparison with other frameworks"): d_img[b] = sqrt( sum_c |F_c^H (M .*
+ * y_c)|^2 ), real float32 [B][Nz][Ny][Nx], no sensitivities.  With the
+ * plan's mask applied to y it is the zero-filled RSS; a fully sampled plan
+ * gives the paper's fully sampled reconstruction.  d_y is never modified;
+ * d_img and d_y must not overlap.
+ */
+SENSE_API sense_status sense_apply_rss(sense_plan plan, const void* d_y, float* d_img, void* stream);
+
+/*
  * Normal operator: d_q = E^H E d_p + lambda d_p, complex64 [B][...].
  * Computed in one fused pass per column (readout transforms cancel).
  * d_p and d_q must not overlap.

@@ -194,6 +194,8 @@ hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32
                     void* y, hipStream_t st);
 hipError_t launch_EH(const Geom& g, const Tables& tb, const void* maps, const void* y, c32* work,
                      c32* x, hipStream_t st);
+// Root-sum-of-squares image of the (masked) k-space, real [B][nz][ny][nx].
+hipError_t launch_rss(const Geom& g, const Tables& tb, const void* y, c32* work, float* out, hipStream_t st);
 // Normal operator from column passes (3D): q = E^H E p + lambda p, with the
 // readout transforms cancelled; fp64 partials of Re<p, q> per block.
 hipError_t launch_EHE_composed(const Geom& g, const Tables& tb, const void* maps, const c32* p, c32* q,

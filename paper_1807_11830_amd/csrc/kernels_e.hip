@@ -277,6 +277,59 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
   }
 }
 
+// Root-sum-of-squares coil combine along y (the paper's RSS reconstruction):
+// for every coil, optional masked load of W[b][c], inverse transform, then
+// |u|^2 summed over the coils; out[b] = sqrt(sum) / sqrt(nx ny nz), real.
+template <int N>
+__global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) rss_colpass_kernel(ColPass P, float* out) {
+  constexpr int T = Len<N>::T;
+  constexpr int E = Len<N>::E;
+  constexpr int TX = col_tile<T>();
+  constexpr int NT = T * TX;
+  using Rad = typename Len<N>::R;
+  __shared__ c32 buf[N * TX];
+  __shared__ c32 tw[N];
+
+  const int tid = threadIdx.x, cx = tid % TX, t = tid / TX;
+  const long nx = P.nx, ny = P.ny;
+  const long x = (long)blockIdx.x * TX + cx;
+  const bool valid = x < nx;
+  const uint32_t xl = (uint32_t)(valid ? x : nx - 1);
+  const long pl = blockIdx.y;  // z plane
+  const long b = blockIdx.z;
+  const long nvox = nx * ny * P.nz;
+  const uint32_t voff = (uint32_t)(pl * ny * nx) + xl + (uint32_t)t * (uint32_t)nx;
+  const uint32_t rstep = (uint32_t)T * (uint32_t)nx;
+  const uint32_t vbytes = (uint32_t)(nvox * 8);
+  for (int i = tid; i < N; i += NT) tw[i] = P.tw[i];
+  __syncthreads();
+  const float sgn = (t & 1) ? -1.f : 1.f;  // output sign is irrelevant to |u|^2
+  LineView<TX> lv{&buf[cx]};
+  const TwTable twt{tw};
+  float acc[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) acc[j] = 0.f;
+  for (int c = 0; c < P.ncoils; ++c) {
+    const Buf bw = make_buf(P.src + (b * P.ncoils + c) * nvox, vbytes);
+    c32 u[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const bool on = P.mask_load ? P.mask[pl * ny + t + T * j] != 0 : true;
+      c32 v = {0.f, 0.f};
+      if (on) v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
+      u[j] = cscale(v, sgn);
+    }
+    fft_line_sb<N, T, +1>(u, t, twt, lv, Rad{});
+#pragma unroll
+    for (int j = 0; j < E; ++j) acc[j] += u[j].re * u[j].re + u[j].im * u[j].im;
+  }
+  if (valid) {
+    float* o = out + b * nvox + voff;
+#pragma unroll
+    for (int j = 0; j < E; ++j) o[(long)j * rstep] = sqrtf(acc[j]) * P.scale;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -482,6 +535,48 @@ hipError_t launch_EHE_composed(const Geom& g, const Tables& tb, const void* maps
   A.mask_load = g.nz > 1 ? 0 : 1;
   A.scale = (float)(1.0 / ((double)g.ny * (double)g.nz));
   return launch_colpass<1, CM_ADJ_COIL>(g, A, g.ny, st);
+}
+
+// RSS image from k-space: the x rows of the sampled lines, the z pass (3D),
+// then the coil combine along y.  out is real [B][nz][ny][nx].
+hipError_t launch_rss(const Geom& g, const Tables& tb, const void* y, c32* work, float* out, hipStream_t st) {
+  const bool is3d = g.nz > 1;
+  hipError_t err = hipErrorInvalidValue;
+  switch (g.kspace_storage) {
+    case ST_C64: err = launch_rows<+1, ST_C64, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st); break;
+    case ST_BF16: err = launch_rows<+1, ST_BF16, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st); break;
+    case ST_FP16: err = launch_rows<+1, ST_FP16, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st); break;
+  }
+  if (err == hipSuccess && is3d) {
+    ColPass Z{};
+    Z.src = work;
+    Z.dst = work;
+    Z.mask = tb.mask_c;
+    Z.tw = tb.tw_z;
+    Z.mask_load = 1;
+    Z.scale = 1.f;
+    err = launch_colpass<2, CM_ADJ>(g, Z, g.nz, st);
+  }
+  if (err != hipSuccess) return err;
+  ColPass P{};
+  P.src = work;
+  P.mask = tb.mask_c;
+  P.tw = tb.tw_y;
+  P.mask_load = is3d ? 0 : 1;
+  P.nx = g.nx;
+  P.ny = g.ny;
+  P.nz = g.nz;
+  P.ncoils = g.ncoils;
+  P.scale = (float)(1.0 / std::sqrt((double)g.nx * (double)g.ny * (double)g.nz));
+  err = hipErrorInvalidValue;
+  dispatch_length(g.ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    constexpr int TX = col_tile<Len<N>::T>();
+    dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)g.nz, (unsigned)g.batch);
+    hipLaunchKernelGGL((rss_colpass_kernel<N>), grid, dim3(Len<N>::T * TX), 0, st, P, out);
+    err = hipGetLastError();
+  });
+  return err;
 }
 
 }  // namespace sense

@@ -358,6 +358,19 @@ sense_status sense_apply_EH(sense_plan p, const void* d_y, void* d_x, void* stre
   return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_apply_EH launch");
 }
 
+sense_status sense_apply_rss(sense_plan p, const void* d_y, float* d_img, void* stream) {
+  sense_status s = check_plan(p);
+  if (s != SENSE_OK) return s;
+  if (!d_y || !d_img) return fail(SENSE_ERR_INVALID, "d_y and d_img must be non-NULL");
+  if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
+  const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
+  const size_t ob = nvox * p->d.batch * sizeof(float);
+  const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
+  if (overlap(d_img, ob, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_img and d_y overlap");
+  hipError_t e = launch_rss(p->g, p->tb, d_y, p->at<c32>(p->L.work), d_img, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_apply_rss launch");
+}
+
 sense_status sense_apply_EHE(sense_plan p, const void* d_p, void* d_q, double lambda, void* stream) {
   sense_status s = check_plan(p);
   if (s != SENSE_OK) return s;

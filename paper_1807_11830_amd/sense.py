@@ -52,7 +52,7 @@ class CgInfo(ctypes.Structure):
 
 
 ABI_FUNCTIONS = ("sense_plan_device_bytes", "sense_plan_create", "sense_plan_destroy",
-                 "sense_apply_E", "sense_apply_EH", "sense_apply_EHE", "sense_cg_solve",
+                 "sense_apply_E", "sense_apply_EH", "sense_apply_EHE", "sense_apply_rss", "sense_cg_solve",
                  "sense_plan_cg_info", "sense_plan_set_profiling", "sense_plan_profile",
                  "sense_plan_set_graphs", "sense_plan_set_maps", "sense_plan_set_coil_groups",
                  "sense_plan_coil_groups", "sense_engine_create", "sense_engine_destroy",
@@ -79,6 +79,7 @@ def lib():
     L.sense_apply_E.argtypes = [P, P, P, P]
     L.sense_apply_EH.argtypes = [P, P, P, P]
     L.sense_apply_EHE.argtypes = [P, P, P, D, P]
+    L.sense_apply_rss.argtypes = [P, P, P, P]
     L.sense_cg_solve.argtypes = [P, P, P, I32, D, D, P, P, P]
     L.sense_plan_cg_info.argtypes = [P, P, P]
     L.sense_plan_set_profiling.argtypes = [P, I32]
@@ -282,6 +283,19 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(lib().sense_apply_EH(self._h, _ptr(y), _ptr(x), _stream(stream)))
         return x
+
+    def rss(self, y: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Root-sum-of-squares image (float32 [B][...]) of the masked k-space."""
+        y = self._ksp(y, "y")
+        if out is None:
+            img = torch.empty(self.image_shape, dtype=torch.float32, device=self.device)
+        else:
+            if out.dtype != torch.float32 or tuple(out.shape) != tuple(self.image_shape) or not out.is_contiguous():
+                raise SenseError(1, f"out must be a contiguous float32 tensor of shape {tuple(self.image_shape)}")
+            img = out
+        with torch.cuda.device(self.device):
+            _check(lib().sense_apply_rss(self._h, _ptr(y), _ptr(img), _stream(stream)))
+        return img
 
     def EHE(self, p: torch.Tensor, lam: float = 0.0, out: torch.Tensor | None = None,
             stream=None) -> torch.Tensor:

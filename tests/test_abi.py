@@ -106,6 +106,7 @@ def test_null_arguments():
     for f, args in (("sense_apply_E", (None, None, None, None)),
                     ("sense_apply_EH", (None, None, None, None)),
                     ("sense_apply_EHE", (None, None, None, 0.0, None)),
+                    ("sense_apply_rss", (None, None, None, None)),
                     ("sense_cg_solve", (None, None, None, 1, 0.0, 0.0, None, None, None)),
                     ("sense_plan_destroy", (None,)),
                     ("sense_plan_set_profiling", (None, 1)),

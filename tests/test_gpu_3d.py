@@ -50,6 +50,18 @@ def test_3d_operators_match_oracle(nz, ny, nx, nc, b, per):
     assert np.all(y[:, :, ~m, :] == 0)
 
 
+def test_3d_rss_matches_oracle():
+    """Zero-filled RSS of a volume: x rows, z pass, y combine."""
+    maps, _, mask = _case3d(16, 32, 48, 3, 2, False, seed=21)
+    y = c64(synth.complex_normal((2, 3, 16, 32, 48), 22))
+    ref = oracle.rss(y * mask[None, None, :, :, None], ndim=3)
+    with sense.Plan(to_dev(maps), mask, batch=2) as plan:
+        got = plan.rss(to_dev(y)).cpu().numpy().astype(np.float64)
+    err = rel_l2(got, ref)
+    log(f"3D RSS rel-L2 {err:.3e}")
+    assert err <= TOL_FP32
+
+
 def test_3d_ehe_ragged_readout():
     maps, x, mask = _case3d(8, 32, 40, 3, 2, False, seed=9)
     with sense.Plan(to_dev(maps), mask, batch=2) as plan:

@@ -98,6 +98,31 @@ def test_E_and_EH_match_oracle(ny, nx, nc, b, per):
     assert e1 <= TOL_FP32 and e2 <= TOL_FP32
 
 
+RSS_CASES = [  # ny, nx, ncoils, batch, fully sampled
+    (160, 160, 8, 2, True),    # the paper's 160x160 / 8-coil frames
+    (64, 80, 3, 1, False),     # zero-filled
+    (32, 8, 2, 1, False),      # ragged: 8 columns in a 16-column tile
+    (256, 48, 4, 1, True),
+]
+
+
+@pytest.mark.parametrize("ny,nx,nc,b,full", RSS_CASES)
+def test_rss_matches_oracle(ny, nx, nc, b, full):
+    log(f"RSS ny={ny} nx={nx} C={nc} B={b} full={full}")
+    maps, _, mask = rand_case(ny, nx, nc, b, False, seed=ny + 3)
+    if full:
+        mask = np.ones(ny, np.uint8)
+    y = c64(synth.complex_normal((b, nc, ny, nx), ny + 4))
+    ref = oracle.rss(y * mask[None, None, :, None])
+    with sense.Plan(to_dev(maps), mask, batch=b) as plan:
+        got = plan.rss(to_dev(y))
+        torch.cuda.synchronize()
+    assert got.dtype == torch.float32 and tuple(got.shape) == (b, ny, nx)
+    err = rel_l2(got.cpu().numpy().astype(np.float64), ref)
+    log(f"  rel-L2 {err:.3e}")
+    assert err <= TOL_FP32
+
+
 def test_adjoint_identity_on_gpu():
     maps, x, mask = rand_case(128, 96, 4, 2, True, seed=9)
     yin = c64(synth.complex_normal((2, 4, 128, 96), 10))
