@@ -11,8 +11,8 @@
 // After the last stage (NS * R = N) that position is t + T*(m + r*E/R): the
 // thread's own register again, so transforms start and end in the same
 // layout and no reordering pass is ever needed.  Between two stages the
-// block exchanges through LDS (one barrier per exchange; two buffers are
-// alternated so the next write never races the previous read).
+// block exchanges through one LDS buffer (a barrier before each exchange
+// write, so it never races the previous read, and one after it).
 //
 // The inverse transform (DIR = +1) runs the same stages with conjugated
 // twiddles, so a forward/inverse pair returns every value to the thread and
@@ -106,52 +106,35 @@ __device__ __forceinline__ void stockham_stage(c32* v, int t, const Tw& tw, View
   });
 }
 
-// Recursive driver over the radix list.  BUF selects the LDS buffer of the
-// next exchange.
-// SB (single buffer): b0 and b1 are the same LDS buffer, so every exchange
-// write first waits for all reads of the previous exchange.
-template <int N, int T, int DIR, int NS, int BUF, bool SB, class View, class Tw, int R, int... Rest>
-__device__ __forceinline__ void fft_stages(c32* v, int t, const Tw& tw, View b0, View b1) {
+// Recursive driver over the radix list.  One LDS buffer serves every
+// exchange: the barrier in front of each exchange write keeps it behind the
+// previous exchange's reads (or the previous transform's), and the one after
+// it makes the write visible.
+template <int N, int T, int DIR, int NS, class View, class Tw, int R, int... Rest>
+__device__ __forceinline__ void fft_stages(c32* v, int t, const Tw& tw, View b) {
   constexpr bool last = sizeof...(Rest) == 0;
-  const View& out = (BUF == 0) ? b0 : b1;
-  if constexpr (SB && !last) {
-    // the write of this stage happens inside stockham_stage after its
-    // butterflies; the barrier in front of the stage keeps it behind the
-    // previous exchange's reads
-    __syncthreads();
-  }
-  stockham_stage<N, T, R, NS, DIR, last>(v, t, tw, out);
+  if constexpr (!last) __syncthreads();
+  stockham_stage<N, T, R, NS, DIR, last>(v, t, tw, b);
   if constexpr (!last) {
     __syncthreads();
     constexpr int E = N / T;
-    sfor<E>([&](auto jc) { v[decltype(jc)::value] = out.at(t + T * decltype(jc)::value); });
-    fft_stages<N, T, DIR, NS * R, BUF ^ 1, SB, View, Tw, Rest...>(v, t, tw, b0, b1);
+    sfor<E>([&](auto jc) { v[decltype(jc)::value] = b.at(t + T * decltype(jc)::value); });
+    fft_stages<N, T, DIR, NS * R, View, Tw, Rest...>(v, t, tw, b);
   }
 }
 
-template <int N, int T, int DIR, int BUF, class View, class Tw, int... Rs>
-__device__ __forceinline__ void fft_line(c32* v, int t, const Tw& tw, View b0, View b1,
-                                         Radices<Rs...>) {
-  static_assert(radix_product(Radices<Rs...>{}) == N, "radices must multiply to N");
-  fft_stages<N, T, DIR, 1, BUF, false, View, Tw, Rs...>(v, t, tw, b0, b1);
-}
-// Single LDS buffer variant (half the LDS, one more barrier per exchange).
+// Transform of one line held as v[j] = line[t + T j] by its T threads
+// (unnormalised; DIR = -1 forward, +1 inverse); the result returns to the
+// same positions.  b is the line's view of the LDS exchange buffer.
 template <int N, int T, int DIR, class View, class Tw, int... Rs>
-__device__ __forceinline__ void fft_line_sb(c32* v, int t, const Tw& tw, View b, Radices<Rs...>) {
+__device__ __forceinline__ void fft_line(c32* v, int t, const Tw& tw, View b, Radices<Rs...>) {
   static_assert(radix_product(Radices<Rs...>{}) == N, "radices must multiply to N");
-  fft_stages<N, T, DIR, 1, 0, true, View, Tw, Rs...>(v, t, tw, b, b);
-}
-template <int N, int T, int DIR, int BUF, class View, int... Rs>
-__device__ __forceinline__ void fft_line(c32* v, int t, const c32* tw, View b0, View b1,
-                                         Radices<Rs...> rad) {
-  fft_line<N, T, DIR, BUF>(v, t, TwTable{tw}, b0, b1, rad);
+  fft_stages<N, T, DIR, 1, View, Tw, Rs...>(v, t, tw, b);
 }
 
-#ifndef SENSE_TWREG_MAX_E
-#define SENSE_TWREG_MAX_E 8
-#endif
 // Twiddle source of the fused kernels: registers for two-stage transforms
-// with at most 16 elements per thread, the LDS table otherwise.
+// with at most 8 elements per thread, the LDS table otherwise.
+constexpr int kTwRegMaxE = 8;
 template <int N, int T, class Rad>
 struct TwChoice {
   using type = TwTable;
@@ -159,14 +142,8 @@ struct TwChoice {
 };
 template <int N, int T, int R1, int R2>
 struct TwChoice<N, T, Radices<R1, R2>> {
-  static constexpr bool regs = (N / T) <= SENSE_TWREG_MAX_E;
+  static constexpr bool regs = (N / T) <= kTwRegMaxE;
   using type = std::conditional_t<regs, TwRegs2<N, T, R1, R2>, TwTable>;
 };
-
-// Number of LDS exchanges of one transform.
-template <int... Rs>
-constexpr int exchanges(Radices<Rs...>) {
-  return (int)sizeof...(Rs) - 1;
-}
 
 }  // namespace sense

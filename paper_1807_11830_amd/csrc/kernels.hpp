@@ -149,10 +149,7 @@ int cg_tiles(long nvox);
 // slice: 50.7 us unsplit, 22.9 us at G = 8; 384^2 x 32 coils x 8 slices:
 // 194 us unsplit, 142 us at G = 2) and costs above it (160 slices of 256^2:
 // 266 us unsplit, 354 us at G = 2).
-#ifndef SENSE_FILL_BLOCKS
-#define SENSE_FILL_BLOCKS 512
-#endif
-constexpr int kFillBlocks = SENSE_FILL_BLOCKS;
+constexpr int kFillBlocks = 512;
 constexpr int kMaxCoilGroups = 16;
 // Automatic coil-group count of a 2D plan (1 for 3D).
 int auto_coil_groups(long nx, long ny, int ncoils, int batch);
@@ -192,10 +189,14 @@ hipError_t launch_combine(const EheParams& P, int batch, bool cg, hipStream_t st
 // Full-grid forward and adjoint operators (2D).
 hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32* x, c32* work,
                     void* y, hipStream_t st);
+// E^H; with ngroups > 1 (2D) the coil sum of the column pass is split into
+// groups whose partials go to part ([G][B][nvox] complex) and are combined.
 hipError_t launch_EH(const Geom& g, const Tables& tb, const void* maps, const void* y, c32* work,
-                     c32* x, hipStream_t st);
-// Root-sum-of-squares image of the (masked) k-space, real [B][nz][ny][nx].
-hipError_t launch_rss(const Geom& g, const Tables& tb, const void* y, c32* work, float* out, hipStream_t st);
+                     c32* x, c32* part, int ngroups, hipStream_t st);
+// Root-sum-of-squares image of the (masked) k-space, real [B][nz][ny][nx];
+// coil groups as for launch_EH (part holds [G][B][nvox] floats).
+hipError_t launch_rss(const Geom& g, const Tables& tb, const void* y, c32* work, float* out, void* part,
+                      int ngroups, hipStream_t st);
 // Normal operator from column passes (3D): q = E^H E p + lambda p, with the
 // readout transforms cancelled; fp64 partials of Re<p, q> per block.
 hipError_t launch_EHE_composed(const Geom& g, const Tables& tb, const void* maps, const c32* p, c32* q,

@@ -224,7 +224,7 @@ hipError_t launch_cg_fused_final(const Geom& g, const CgVectors& v, int K, const
 }
 
 // Coil-group combine of one problem row: q = sum_g qpart[g] + lambda p, the
-// groups added in index order.  CG mode (P.state set) also emits the fp64
+// groups added in index order (no lambda p when p is null: the E^H combine).  CG mode (P.state set) also emits the fp64
 // partials Re<p,q>, Re<r,q>, <q,q>, <r,r> of launch k into part4[k & 1]
 // (one entry per block of this kernel) and skips a problem that has stopped.
 __device__ __forceinline__ void combine_body(const EheParams& P, const int b, const int tile, const bool cg) {
@@ -249,7 +249,8 @@ __device__ __forceinline__ void combine_body(const EheParams& P, const int b, co
         qs.b.re += t.b.re;
         qs.b.im += t.b.im;
       }
-      const c32x2 pv = *reinterpret_cast<const c32x2*>(pk + i);
+      c32x2 pv = {{0.f, 0.f}, {0.f, 0.f}};
+      if (pk) pv = *reinterpret_cast<const c32x2*>(pk + i);
       c32x2 qv;
       qv.a = {qs.a.re + lam * pv.a.re, qs.a.im + lam * pv.a.im};
       qv.b = {qs.b.re + lam * pv.b.re, qs.b.im + lam * pv.b.im};

@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
   for (int j = 0; j < E; ++j) v[j] = valid ? cscale(load_c<ST_IN>(in, t + T * j), sgn) : c32{0.f, 0.f};
   __syncthreads();
   LineView<1> lv{&buf[l * LDL]};
-  fft_line_sb<N, T, DIR>(v, t, TwTable{tw}, lv, Rad{});
+  fft_line<N, T, DIR>(v, t, TwTable{tw}, lv, Rad{});
   if (valid) {
     TO* out = static_cast<TO*>(P.out) + off;
     const float s = sgn * P.scale;
@@ -123,18 +123,21 @@ struct ColPass {
   int mask_load;
   float scale;
   float lambda;
+  // ADJ_COIL / RSS coil groups: with ngroups > 1 grid z is batch x groups,
+  // and each block writes its group's partial sum to part[g][b] (complex
+  // for ADJ_COIL, real for RSS) for a combine pass
+  void* part;
+  long part_gstride;  // elements between groups (batch * nvox)
+  int ngroups;
 };
 
 // Columns per block of a pass along AXIS.  Along z consecutive rows of a
 // column are a whole x-y plane apart, so each row segment is its own DRAM
 // page: wider segments (32 columns, 256 bytes) where the block stays within
 // 256 threads.
-#ifndef SENSE_ZTX
-#define SENSE_ZTX 32
-#endif
 template <int T, int AXIS>
 constexpr int pass_tile() {
-  return (AXIS == 2 && T * SENSE_ZTX <= 256) ? SENSE_ZTX : col_tile<T>();
+  return (AXIS == 2 && T * 32 <= 256) ? 32 : col_tile<T>();
 }
 
 template <int N, int AXIS, int MODE, int ST>
@@ -196,17 +199,17 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
       }
     }
     if constexpr (MODE == CM_ADJ) {
-      fft_line_sb<N, T, +1>(u, t, twt, lv, Rad{});
+      fft_line<N, T, +1>(u, t, twt, lv, Rad{});
     } else if constexpr (MODE == CM_PROJ) {
       static_assert(AXIS == 2, "the projector runs along z");
-      fft_line_sb<N, T, -1>(u, t, twt, lv, Rad{});
+      fft_line<N, T, -1>(u, t, twt, lv, Rad{});
       // checkerboards of the forward output and inverse input cancel
 #pragma unroll
       for (int j = 0; j < E; ++j)
         if (!mask_at(t + T * j)) u[j] = {0.f, 0.f};
-      fft_line_sb<N, T, +1>(u, t, twt, lv, Rad{});
+      fft_line<N, T, +1>(u, t, twt, lv, Rad{});
     } else {
-      fft_line_sb<N, T, -1>(u, t, twt, lv, Rad{});
+      fft_line<N, T, -1>(u, t, twt, lv, Rad{});
     }
     if (valid) {
       const Buf bd = make_buf(P.dst + bc * nvox, vbytes);
@@ -218,14 +221,14 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
       }
     }
   } else {
-    const long b = blockIdx.z;
+    const int G = P.ngroups;
+    const long b = blockIdx.z / G;
+    const int grp = (int)(blockIdx.z % G);
+    const int c0 = (int)((long)grp * P.ncoils / G), c1 = (int)((long)(grp + 1) * P.ncoils / G);
     c32 acc[E];
 #pragma unroll
     for (int j = 0; j < E; ++j) acc[j] = {0.f, 0.f};
-#ifndef SENSE_ADJ_SPRE
-#define SENSE_ADJ_SPRE 1
-#endif
-    for (int c = 0; c < P.ncoils; ++c) {
+    for (int c = c0; c < c1; ++c) {
       const Buf bw = make_buf(P.src + (b * P.ncoils + c) * nvox, vbytes);
       const Buf bs = make_buf(static_cast<const SType*>(P.maps) + b * P.maps_bstride + (long)c * nvox,
                               (uint32_t)(nvox * sizeof(SType)));
@@ -240,19 +243,21 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
       // the coil's maps are loaded before the transform so their latency
       // hides behind it (measured 16% faster for 256^2 x 12 coils x 160
       // slices than loading them after it, at one wave less per SIMD)
-      [[maybe_unused]] c32 sv[SENSE_ADJ_SPRE ? E : 1];
-      if constexpr (SENSE_ADJ_SPRE != 0) {
+      c32 sv[E];
 #pragma unroll
-        for (int j = 0; j < E; ++j) sv[j] = buf_load_st<ST>(bs, voff + (uint32_t)j * rstep, 0);
-      }
-      fft_line_sb<N, T, +1>(u, t, twt, lv, Rad{});
+      for (int j = 0; j < E; ++j) sv[j] = buf_load_st<ST>(bs, voff + (uint32_t)j * rstep, 0);
+      fft_line<N, T, +1>(u, t, twt, lv, Rad{});
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
-        c32 s;
-        if constexpr (SENSE_ADJ_SPRE != 0) s = sv[j];
-        else s = buf_load_st<ST>(bs, voff + (uint32_t)j * rstep, 0);
-        acc[j] = cfma_conj(acc[j], s, cscale(u[j], sgn));
+      for (int j = 0; j < E; ++j) acc[j] = cfma_conj(acc[j], sv[j], cscale(u[j], sgn));
+    }
+    if (G > 1) {
+      // this group's partial coil sum (scaled); the combine pass adds them
+      if (valid) {
+        const Buf bg = make_buf(static_cast<c32*>(P.part) + grp * P.part_gstride + b * nvox, vbytes);
+#pragma unroll
+        for (int j = 0; j < E; ++j) buf_store_c64(bg, cscale(acc[j], P.scale), (voff + (uint32_t)j * rstep) * 8u, 0);
       }
+      return;
     }
     const Buf bd = make_buf(P.dst + b * nvox, vbytes);
     double eta = 0.0;
@@ -296,7 +301,10 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) rss_colpass
   const bool valid = x < nx;
   const uint32_t xl = (uint32_t)(valid ? x : nx - 1);
   const long pl = blockIdx.y;  // z plane
-  const long b = blockIdx.z;
+  const int G = P.ngroups;
+  const long b = blockIdx.z / G;
+  const int grp = (int)(blockIdx.z % G);
+  const int c0 = (int)((long)grp * P.ncoils / G), c1 = (int)((long)(grp + 1) * P.ncoils / G);
   const long nvox = nx * ny * P.nz;
   const uint32_t voff = (uint32_t)(pl * ny * nx) + xl + (uint32_t)t * (uint32_t)nx;
   const uint32_t rstep = (uint32_t)T * (uint32_t)nx;
@@ -309,7 +317,7 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) rss_colpass
   float acc[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) acc[j] = 0.f;
-  for (int c = 0; c < P.ncoils; ++c) {
+  for (int c = c0; c < c1; ++c) {
     const Buf bw = make_buf(P.src + (b * P.ncoils + c) * nvox, vbytes);
     c32 u[E];
 #pragma unroll
@@ -319,15 +327,31 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) rss_colpass
       if (on) v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
       u[j] = cscale(v, sgn);
     }
-    fft_line_sb<N, T, +1>(u, t, twt, lv, Rad{});
+    fft_line<N, T, +1>(u, t, twt, lv, Rad{});
 #pragma unroll
     for (int j = 0; j < E; ++j) acc[j] += u[j].re * u[j].re + u[j].im * u[j].im;
   }
-  if (valid) {
-    float* o = out + b * nvox + voff;
+  if (!valid) return;
+  if (G > 1) {
+    // this group's partial sum of squares; the combine pass finishes
+    float* o = static_cast<float*>(P.part) + grp * P.part_gstride + b * nvox + voff;
 #pragma unroll
-    for (int j = 0; j < E; ++j) o[(long)j * rstep] = sqrtf(acc[j]) * P.scale;
+    for (int j = 0; j < E; ++j) o[(long)j * rstep] = acc[j];
+    return;
   }
+  float* o = out + b * nvox + voff;
+#pragma unroll
+  for (int j = 0; j < E; ++j) o[(long)j * rstep] = sqrtf(acc[j]) * P.scale;
+}
+
+// RSS combine of G partial sums of squares, added in group order.
+__global__ void __launch_bounds__(256) rss_combine_kernel(const float* __restrict__ part, long gstride, int G,
+                                                          long n, float scale, float* __restrict__ out) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float a = part[i];
+  for (int g = 1; g < G; ++g) a += part[(long)g * gstride + i];
+  out[i] = sqrtf(a) * scale;
 }
 
 // ---------------------------------------------------------------------------
@@ -380,6 +404,7 @@ static double axis_scale(long n) {
 template <int AXIS, int MODE>
 static hipError_t launch_colpass(const Geom& g, ColPass P, long n, hipStream_t st) {
   hipError_t err = hipErrorInvalidValue;
+  if (P.ngroups < 1) P.ngroups = 1;
   P.nx = g.nx;
   P.ny = g.ny;
   P.nz = g.nz;
@@ -389,7 +414,8 @@ static hipError_t launch_colpass(const Geom& g, ColPass P, long n, hipStream_t s
     constexpr int N = decltype(nc)::value;
     constexpr int TX = pass_tile<Len<N>::T, AXIS>();
     const long planes = AXIS == 1 ? g.nz : g.ny;
-    const long zdim = MODE == CM_ADJ_COIL ? g.batch : (long)g.batch * g.ncoils;
+    const long zdim = MODE == CM_ADJ_COIL ? (long)g.batch * (P.ngroups > 0 ? P.ngroups : 1)
+                                          : (long)g.batch * g.ncoils;
     dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)planes, (unsigned)zdim);
     dim3 block(Len<N>::T * TX);
     switch (g.maps_storage) {
@@ -456,7 +482,8 @@ hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32
 // The adjoint passes after the x rows: z-pass (3D, masked loads) and the
 // y-pass with the conjugate-sensitivity coil sum into x.
 static hipError_t launch_EH_tail(const Geom& g, const Tables& tb, const void* maps, c32* work, c32* x,
-                                 const c32* addp, float lambda, double* eta_part, hipStream_t st) {
+                                 const c32* addp, float lambda, double* eta_part, c32* part, int ngroups,
+                                 hipStream_t st) {
   const bool is3d = g.nz > 1;
   hipError_t err = hipSuccess;
   if (is3d) {
@@ -481,11 +508,24 @@ static hipError_t launch_EH_tail(const Geom& g, const Tables& tb, const void* ma
   P.tw = tb.tw_y;
   P.mask_load = is3d ? 0 : 1;
   P.scale = (float)(axis_scale(g.nx) * axis_scale(g.ny) * axis_scale(g.nz));
-  return launch_colpass<1, CM_ADJ_COIL>(g, P, g.ny, st);
+  const bool split = ngroups > 1 && part && !addp && !eta_part;
+  P.ngroups = split ? ngroups : 1;
+  P.part = part;
+  P.part_gstride = (long)g.batch * g.nx * g.ny * g.nz;
+  err = launch_colpass<1, CM_ADJ_COIL>(g, P, g.ny, st);
+  if (err != hipSuccess || !split) return err;
+  // x = sum of the group partials, in group order
+  EheParams C{};
+  C.qpart = part;
+  C.qpart_gstride = P.part_gstride;
+  C.ngroups = ngroups;
+  C.q = x;
+  C.nvox = g.nx * g.ny * g.nz;
+  return launch_combine(C, g.batch, false, st);
 }
 
 hipError_t launch_EH(const Geom& g, const Tables& tb, const void* maps, const void* y, c32* work,
-                     c32* x, hipStream_t st) {
+                     c32* x, c32* part, int ngroups, hipStream_t st) {
   hipError_t err = hipErrorInvalidValue;
   switch (g.kspace_storage) {
     case ST_C64: err = launch_rows<+1, ST_C64, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st); break;
@@ -493,7 +533,7 @@ hipError_t launch_EH(const Geom& g, const Tables& tb, const void* maps, const vo
     case ST_FP16: err = launch_rows<+1, ST_FP16, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st); break;
   }
   if (err != hipSuccess) return err;
-  return launch_EH_tail(g, tb, maps, work, x, nullptr, 0.f, nullptr, st);
+  return launch_EH_tail(g, tb, maps, work, x, nullptr, 0.f, nullptr, part, ngroups, st);
 }
 
 // Normal operator from column passes (3D).  With a (ky, kz) mask the
@@ -539,7 +579,8 @@ hipError_t launch_EHE_composed(const Geom& g, const Tables& tb, const void* maps
 
 // RSS image from k-space: the x rows of the sampled lines, the z pass (3D),
 // then the coil combine along y.  out is real [B][nz][ny][nx].
-hipError_t launch_rss(const Geom& g, const Tables& tb, const void* y, c32* work, float* out, hipStream_t st) {
+hipError_t launch_rss(const Geom& g, const Tables& tb, const void* y, c32* work, float* out, void* part,
+                      int ngroups, hipStream_t st) {
   const bool is3d = g.nz > 1;
   hipError_t err = hipErrorInvalidValue;
   switch (g.kspace_storage) {
@@ -568,15 +609,24 @@ hipError_t launch_rss(const Geom& g, const Tables& tb, const void* y, c32* work,
   P.nz = g.nz;
   P.ncoils = g.ncoils;
   P.scale = (float)(1.0 / std::sqrt((double)g.nx * (double)g.ny * (double)g.nz));
+  const bool split = ngroups > 1 && part;
+  P.ngroups = split ? ngroups : 1;
+  P.part = part;
+  const long nvox = g.nx * g.ny * g.nz;
+  P.part_gstride = (long)g.batch * nvox;
   err = hipErrorInvalidValue;
   dispatch_length(g.ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     constexpr int TX = col_tile<Len<N>::T>();
-    dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)g.nz, (unsigned)g.batch);
+    dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)g.nz, (unsigned)(g.batch * P.ngroups));
     hipLaunchKernelGGL((rss_colpass_kernel<N>), grid, dim3(Len<N>::T * TX), 0, st, P, out);
     err = hipGetLastError();
   });
-  return err;
+  if (err != hipSuccess || !split) return err;
+  const long n = (long)g.batch * nvox;
+  hipLaunchKernelGGL(rss_combine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     static_cast<const float*>(part), P.part_gstride, P.ngroups, n, P.scale, out);
+  return hipGetLastError();
 }
 
 }  // namespace sense

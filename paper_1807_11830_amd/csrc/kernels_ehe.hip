@@ -35,13 +35,9 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   constexpr int TX = EheLen<N>::TX;
   constexpr int NT = T * TX;
   using Rad = typename EheLen<N>::R;
-  constexpr int NEX = exchanges(Rad{});
 
-#ifndef SENSE_EHE_SINGLEBUF
-#define SENSE_EHE_SINGLEBUF 1
-#endif
-  constexpr int NBUF = SENSE_EHE_SINGLEBUF ? 1 : 2;
-  __shared__ c32 xbuf[NBUF][N * TX];
+  // one LDS exchange buffer (each stage boundary waits for its readers)
+  __shared__ c32 xbuf[N * TX];
   __shared__ c32 tw[N];
   __shared__ float mu[N];
   __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
@@ -75,14 +71,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   const uint32_t rstep = (uint32_t)T * (uint32_t)nx;      // rows t -> t + T
   const uint32_t img_bytes = (uint32_t)(nvox * (long)sizeof(c32));
   const Buf bq = make_buf(P.q + (long)b * nvox, img_bytes);
-#ifndef SENSE_EHE_RREG
-#define SENSE_EHE_RREG 0
-#endif
-  // CG keeps the new residual in registers for Re<r, q> (RREG), or re-reads
-  // the tile it wrote (fewer VGPRs, one more pass over r through the caches)
-  constexpr bool RREG = SENSE_EHE_RREG != 0;
   c32 p[E], q[E];
-  [[maybe_unused]] c32 r[RREG ? E : 1];
   [[maybe_unused]] double rho_acc = 0.0;
   if constexpr (!CG) {
     const Buf bp = make_buf(P.p_in + (long)b * nvox, img_bytes);
@@ -108,9 +97,6 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     // two groups of loads hold registers (the transform's are still free).
     // Launch 0 runs the same code: alpha = beta = 0 and q is zero there
     // (the init kernel clears it), so the update leaves x, r, p as they are.
-#ifndef SENSE_EHE_PIPE
-#define SENSE_EHE_PIPE 1
-#endif
     constexpr int G = E % 4 == 0 ? 4 : 1;
     constexpr int NG = E / G;
     const uint32_t lo = voff * 8u;
@@ -143,26 +129,17 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
           buf_store_c64(bpo, pv, lo, so);
         }
         p[j] = pv;
-        if constexpr (RREG) r[j] = rv;
-        else if (valid) rho_acc += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
+        if (valid) rho_acc += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
         q[j] = {0.f, 0.f};
       });
     };
-    if constexpr (SENSE_EHE_PIPE != 0 && NG > 1) {
-      load_group(std::integral_constant<int, 0>{}, 0);
-      sfor<NG>([&](auto gc) {
-        constexpr int g = decltype(gc)::value;
-        if constexpr (g + 1 < NG) load_group(std::integral_constant<int, g + 1>{}, (g + 1) & 1);
-        asm volatile("" ::: "memory");
-        update_group(gc, g & 1);
-      });
-    } else {
-      sfor<NG>([&](auto gc) {
-        load_group(gc, 0);
-        update_group(gc, 0);
-        asm volatile("" ::: "memory");
-      });
-    }
+    load_group(std::integral_constant<int, 0>{}, 0);
+    sfor<NG>([&](auto gc) {
+      constexpr int g = decltype(gc)::value;
+      if constexpr (g + 1 < NG) load_group(std::integral_constant<int, g + 1>{}, (g + 1) & 1);
+      asm volatile("" ::: "memory");
+      update_group(gc, g & 1);
+    });
   }
   __syncthreads();
 
@@ -174,7 +151,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   using SType = typename StorageT<ST>::T;
   const SType* S = static_cast<const SType*>(P.maps) + (long)b * P.maps_bstride;
   const uint32_t coil_bytes = (uint32_t)(nvox * (long)sizeof(SType));
-  LineView<TX> v0{&xbuf[0][cx]}, v1{&xbuf[NBUF - 1][cx]};
+  LineView<TX> lv{&xbuf[cx]};
 
   auto load_s = [&](c32* s, int c) {
     const Buf bs = make_buf(S + (long)c * nvox, coil_bytes);
@@ -182,44 +159,27 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     for (int j = 0; j < E; ++j) s[j] = buf_load_st<ST>(bs, voff, (uint32_t)j * rstep);
   };
   // One coil: u = S p, forward transform, mask, inverse transform,
-  // q += conj(S) u.  The transform pair uses an even number of exchanges,
-  // so every coil starts on LDS buffer 0.
+  // q += conj(S) u.
   auto coil = [&](const c32* s) {
     c32 u[E];
 #pragma unroll
     for (int j = 0; j < E; ++j) u[j] = cmul(s[j], p[j]);
-    if constexpr (NBUF == 1) fft_line_sb<N, T, -1>(u, t, twsrc, v0, Rad{});
-    else fft_line<N, T, -1, 0>(u, t, twsrc, v0, v1, Rad{});
+    fft_line<N, T, -1>(u, t, twsrc, lv, Rad{});
 #pragma unroll
     for (int j = 0; j < E; ++j) u[j] = cscale(u[j], mu[t + T * j]);
-    if constexpr (NBUF == 1) fft_line_sb<N, T, +1>(u, t, twsrc, v0, Rad{});
-    else fft_line<N, T, +1, NEX & 1>(u, t, twsrc, v0, v1, Rad{});
+    fft_line<N, T, +1>(u, t, twsrc, lv, Rad{});
 #pragma unroll
     for (int j = 0; j < E; ++j) q[j] = cfma_conj(q[j], s[j], u[j]);
   };
 
-#ifndef SENSE_EHE_PREFETCH
-#define SENSE_EHE_PREFETCH 0
-#endif
+  // this block's coil group
   const int c0 = (int)((long)grp * P.ncoils / P.ngroups);
   const int c1 = (int)((long)(grp + 1) * P.ncoils / P.ngroups);
-#if SENSE_EHE_PREFETCH
-  // Maps of coil c+1 are loaded while coil c is transformed.
-  c32 sc[E], sn[E];
-  load_s(sc, c0);
-  for (int c = c0; c < c1; ++c) {
-    if (c + 1 < c1) load_s(sn, c + 1);
-    coil(sc);
-#pragma unroll
-    for (int j = 0; j < E; ++j) sc[j] = sn[j];
-  }
-#else
   for (int c = c0; c < c1; ++c) {
     c32 sc[E];
     load_s(sc, c);
     coil(sc);
   }
-#endif
 
   if (P.ngroups > 1) {
     // partial coil sum of this group; the combine pass does the rest
@@ -248,27 +208,23 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     // q = A p; fp64 partials of Re<p,q>, Re<r,q>, <q,q>, <r,r> for the
     // next launch (alpha, the recurrence for beta, and the true rho_k)
     double acc[4] = {0.0, 0.0, 0.0, rho_acc};
-    // the residual written by the prologue, re-read (all loads before the
-    // first q store, so no wait covers a store)
-    c32 rr[RREG ? 1 : E];
-    if constexpr (!RREG) {
-      const Buf brr = make_buf(P.r_out + (long)b * nvox, img_bytes);
+    // the residual written by the prologue, re-read rather than kept in
+    // registers across the transforms (all loads before the first q store,
+    // so no wait covers a store)
+    c32 rr[E];
+    const Buf brr = make_buf(P.r_out + (long)b * nvox, img_bytes);
 #pragma unroll
-      for (int j = 0; j < E; ++j) rr[j] = buf_load_c64(brr, voff * 8u, (uint32_t)j * rstep * 8u);
-      asm volatile("" ::: "memory");
-    }
+    for (int j = 0; j < E; ++j) rr[j] = buf_load_c64(brr, voff * 8u, (uint32_t)j * rstep * 8u);
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       c32 qq = {q[j].re + P.lambda * p[j].re, q[j].im + P.lambda * p[j].im};
-      c32 rv;
-      if constexpr (RREG) rv = r[j];
-      else rv = rr[j];
+      const c32 rv = rr[j];
       if (valid) {
         buf_store_c64(bq, qq, voff * 8u, (uint32_t)j * rstep * 8u);
         acc[0] += (double)p[j].re * (double)qq.re + (double)p[j].im * (double)qq.im;
         acc[1] += (double)rv.re * (double)qq.re + (double)rv.im * (double)qq.im;
         acc[2] += (double)qq.re * (double)qq.re + (double)qq.im * (double)qq.im;
-        if constexpr (RREG) acc[3] += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
       }
     }
     double* out = P.part4 + (((long)(P.k & 1) * P.part_batch + b) * P.part_tiles + tile) * 4;

@@ -48,29 +48,16 @@ struct EheLen : Len<N> {
   static constexpr int TX = col_tile<Len<N>::T>();
 };
 
-#ifndef SENSE_EHE256_T
-#define SENSE_EHE256_T 16
-#endif
-#ifndef SENSE_EHE_TX
-#define SENSE_EHE_TX 16
-#endif
-#if SENSE_EHE256_T == 32
-template <>
-struct EheLen<256> {
-  static constexpr int T = 32;
-  static constexpr int E = 8;
-  using R = Radices<8, 8, 4>;
-  static constexpr int TX = 16;
-};
-#else
+// 256 = 16 * 16: two radix-16 stages over 16 threads per column (measured
+// faster than 32 threads x 8 elements with radices 8, 8, 4, and than 8 or
+// 32 columns per block).
 template <>
 struct EheLen<256> {
   static constexpr int T = 16;
   static constexpr int E = 16;
   using R = Radices<16, 16>;
-  static constexpr int TX = SENSE_EHE_TX;
+  static constexpr int TX = 16;
 };
-#endif
 template <>
 struct EheLen<128> {
   static constexpr int T = 16;
@@ -80,11 +67,9 @@ struct EheLen<128> {
 };
 // 384 = 12 * 4 * 4 * 2 over 32 threads per column: 12 elements per thread
 // instead of 24 keeps the kernel within 3 waves per SIMD, and twice the
-// threads per column fill the chip at small batches.
-#ifndef SENSE_EHE384_T
-#define SENSE_EHE384_T 32
-#endif
-#if SENSE_EHE384_T == 32
+// threads per column fill the chip at small batches.  (320 stays at 16
+// threads x 20 elements: 32 threads would need six stages, 10 x 2^5, and
+// measured slower.)
 template <>
 struct EheLen<384> {
   static constexpr int T = 32;
@@ -92,19 +77,6 @@ struct EheLen<384> {
   using R = Radices<12, 4, 4, 2>;
   static constexpr int TX = 8;
 };
-#endif
-#ifndef SENSE_EHE320_T
-#define SENSE_EHE320_T 16
-#endif
-#if SENSE_EHE320_T == 32
-template <>
-struct EheLen<320> {
-  static constexpr int T = 32;
-  static constexpr int E = 10;
-  using R = Radices<10, 2, 2, 2, 2, 2>;
-  static constexpr int TX = 8;
-};
-#endif
 template <>
 struct EheLen<192> {
   static constexpr int T = 16;

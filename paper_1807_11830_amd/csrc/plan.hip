@@ -147,7 +147,8 @@ static sense_status timed_ehe_begin(sense_plan p, hipStream_t st, hipEvent_t* st
 hipError_t enqueue_solve_begin(sense_plan p, const void* d_y, c32* x, const CgArgs& cg,
                                       hipStream_t st) {
   c32* r = p->at<c32>(p->L.r);
-  hipError_t e = launch_EH(p->g, p->tb, p->maps, d_y, p->at<c32>(p->L.work), r, st);
+  hipError_t e = launch_EH(p->g, p->tb, p->maps, d_y, p->at<c32>(p->L.work), r, p->vectors(x).qpart,
+                           p->ngroups, st);
   if (e == hipSuccess) e = launch_cg_init(p->g, r, x, r, p->at<c32>(p->L.p), p->at<c32>(p->L.q), cg, st);
   return e;
 }
@@ -354,7 +355,7 @@ sense_status sense_apply_EH(sense_plan p, const void* d_y, void* d_x, void* stre
   const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
   if (overlap(d_x, xb, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_x and d_y overlap");
   hipError_t e = launch_EH(p->g, p->tb, p->maps, d_y, p->at<c32>(p->L.work), static_cast<c32*>(d_x),
-                           static_cast<hipStream_t>(stream));
+                           p->vectors(nullptr).qpart, p->ngroups, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_apply_EH launch");
 }
 
@@ -367,7 +368,8 @@ sense_status sense_apply_rss(sense_plan p, const void* d_y, float* d_img, void* 
   const size_t ob = nvox * p->d.batch * sizeof(float);
   const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
   if (overlap(d_img, ob, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_img and d_y overlap");
-  hipError_t e = launch_rss(p->g, p->tb, d_y, p->at<c32>(p->L.work), d_img, static_cast<hipStream_t>(stream));
+  hipError_t e = launch_rss(p->g, p->tb, d_y, p->at<c32>(p->L.work), d_img, p->vectors(nullptr).qpart,
+                            p->ngroups, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_apply_rss launch");
 }
 

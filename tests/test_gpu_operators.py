@@ -39,19 +39,25 @@ def test_ehe_matches_oracle(ny, nx, nc, b, per):
 
 def test_ehe_coil_groups():
     """5 column tiles x 2 slices fill few blocks, so the plan splits the 7
-    coils into 3 groups (2, 2 and 3 coils); a forced smaller, uneven split
-    and no split give the same operator to the fp32 bar."""
-    maps, x, mask = rand_case(128, 72, 7, 2, True, seed=9)
+    coils into 3 groups (2, 2 and 3 coils) for E^H E, E^H and RSS; a forced
+    smaller, uneven split and no split give the same operators to the fp32
+    bar."""
+    maps, x, mask = rand_case(128, 80, 7, 2, True, seed=9)
+    y = c64(synth.complex_normal((2, 7, 128, 80), 10))
     ref = oracle.A(x, maps, mask, lam=0.2)
+    ref_h = oracle.EH(y, maps, mask)
+    ref_r = oracle.rss(y * mask[None, None, :, None])
     with sense.Plan(to_dev(maps), mask, batch=2) as plan:
         g, gmax = plan.coil_groups()
         assert g == gmax == 3
         for G in (1, 2, 3):
             plan.set_coil_groups(G)
             q = to_host(plan.EHE(to_dev(x), lam=0.2))
-            err = rel_l2(q, ref)
-            log(f"  G={G} rel-L2 {err:.3e}")
-            assert err <= TOL_FP32
+            xh = to_host(plan.EH(to_dev(y)))
+            rs = plan.rss(to_dev(y)).cpu().numpy().astype(np.float64)
+            errs = rel_l2(q, ref), rel_l2(xh, ref_h), rel_l2(rs, ref_r)
+            log(f"  G={G} rel-L2 EHE {errs[0]:.3e} EH {errs[1]:.3e} RSS {errs[2]:.3e}")
+            assert max(errs) <= TOL_FP32
         with pytest.raises(sense.SenseError, match="coil groups"):
             plan.set_coil_groups(gmax + 1)
         plan.set_coil_groups(0)
