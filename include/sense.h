@@ -91,6 +91,9 @@ typedef struct {
   int32_t maps_storage;   /* sense_storage of the sensitivity maps */
   int32_t kspace_storage; /* sense_storage of k-space y */
   int32_t maps_shared;    /* 1: one [C][...] map set serves every batch element */
+  int32_t kspace_compact; /* 0: full grid [B][C][Nz][Ny][Nx]; 1: sampled lines
+                             only, [B][C][L][Nx] with the L sampled (z, y)
+                             lines in increasing z * Ny + y order */
 } sense_desc;
 
 /* Per batch element result of sense_cg_solve (24 bytes). */
@@ -139,7 +142,8 @@ SENSE_API sense_status sense_plan_destroy(sense_plan plan);
 
 /*
  * Forward operator: d_y[B][C][Nz][Ny][Nx] (kspace_storage) = E d_x.
- * Unsampled locations are written as zeros.  d_x complex64 [B][...].
+ * Unsampled locations are written as zeros (full grid) or not stored at all
+ * (kspace_compact: d_y is [B][C][L][Nx]).  d_x complex64 [B][...].
  * d_x and d_y must not overlap.
  */
 SENSE_API sense_status sense_apply_E(sense_plan plan, const void* d_x, void* d_y, void* stream);

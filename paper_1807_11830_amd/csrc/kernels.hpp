@@ -48,6 +48,7 @@ struct Geom {
   long maps_bstride;  // elements between batch elements of the maps (0 = shared)
   int maps_storage;   // Storage
   int kspace_storage; // Storage
+  int kspace_compact; // k-space holds the sampled lines only
 };
 
 // Device tables owned by the plan.

@@ -41,6 +41,7 @@ struct RowParams {
   long nx;
   const c32* tw;
   float scale;
+  int compact_in, compact_out;  // that side holds only the listed rows, in list order
 };
 
 template <int N, int DIR, int ST_IN, int ST_OUT>
@@ -60,15 +61,18 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
   const bool valid = L < P.lines;
   for (int i = tid; i < N; i += ROW_NT) tw[i] = P.tw[i];
 
-  long off = 0;
+  long off_in = 0, off_out = 0;
   if (valid) {
     const long bc = L / P.nrows;
-    const long row = P.rows[L % P.nrows];
-    off = (bc * P.rows_total + row) * P.nx;
+    const long li = L % P.nrows;
+    const long full = (bc * P.rows_total + P.rows[li]) * P.nx;
+    const long compact = (bc * P.nrows + li) * P.nx;
+    off_in = P.compact_in ? compact : full;
+    off_out = P.compact_out ? compact : full;
   }
   using TI = typename StorageT<ST_IN>::T;
   using TO = typename StorageT<ST_OUT>::T;
-  const TI* in = static_cast<const TI*>(P.in) + off;
+  const TI* in = static_cast<const TI*>(P.in) + off_in;
   const float sgn = (t & 1) ? -1.f : 1.f;
   c32 v[E];
 #pragma unroll
@@ -77,7 +81,7 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
   LineView<1> lv{&buf[l * LDL]};
   fft_line<N, T, DIR>(v, t, TwTable{tw}, lv, Rad{});
   if (valid) {
-    TO* out = static_cast<TO*>(P.out) + off;
+    TO* out = static_cast<TO*>(P.out) + off_out;
     const float s = sgn * P.scale;
 #pragma unroll
     for (int j = 0; j < E; ++j) store_c<ST_OUT>(out, t + T * j, cscale(v[j], s));
@@ -363,6 +367,9 @@ static hipError_t launch_rows(const Geom& g, const c32* tw, const void* in, void
                               const int32_t* rows, int nrows, float scale, hipStream_t st) {
   if (nrows == 0) return hipSuccess;
   RowParams P{};
+  // the k-space side: the output of the forward rows, the input of the inverse
+  P.compact_in = DIR > 0 ? g.kspace_compact : 0;
+  P.compact_out = DIR < 0 ? g.kspace_compact : 0;
   P.in = in;
   P.out = out;
   P.rows = rows;
@@ -464,15 +471,15 @@ hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32
   switch (g.kspace_storage) {
     case ST_C64:
       err = launch_rows<-1, ST_C64, ST_C64>(g, tb.tw_x, work, y, tb.rows_s, tb.n_rows_s, sc, st);
-      if (err == hipSuccess) err = launch_zero_rows<ST_C64>(g, y, tb.rows_u, tb.n_rows_u, st);
+      if (err == hipSuccess && !g.kspace_compact) err = launch_zero_rows<ST_C64>(g, y, tb.rows_u, tb.n_rows_u, st);
       break;
     case ST_BF16:
       err = launch_rows<-1, ST_C64, ST_BF16>(g, tb.tw_x, work, y, tb.rows_s, tb.n_rows_s, sc, st);
-      if (err == hipSuccess) err = launch_zero_rows<ST_BF16>(g, y, tb.rows_u, tb.n_rows_u, st);
+      if (err == hipSuccess && !g.kspace_compact) err = launch_zero_rows<ST_BF16>(g, y, tb.rows_u, tb.n_rows_u, st);
       break;
     case ST_FP16:
       err = launch_rows<-1, ST_C64, ST_FP16>(g, tb.tw_x, work, y, tb.rows_s, tb.n_rows_s, sc, st);
-      if (err == hipSuccess) err = launch_zero_rows<ST_FP16>(g, y, tb.rows_u, tb.n_rows_u, st);
+      if (err == hipSuccess && !g.kspace_compact) err = launch_zero_rows<ST_FP16>(g, y, tb.rows_u, tb.n_rows_u, st);
       break;
     default: err = hipErrorInvalidValue;
   }

@@ -37,6 +37,13 @@ static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 size_t storage_bytes(int st) { return st == ST_C64 ? 8 : 4; }
 
+// Bytes of the plan's k-space argument (full grid or sampled lines only).
+static size_t kspace_bytes(const sense_plan_s* p) {
+  const size_t per_coil = p->d.kspace_compact ? (size_t)p->n_rows_s * p->d.nx
+                                              : (size_t)p->d.nx * p->d.ny * p->d.nz;
+  return per_coil * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
+}
+
 
 static Layout make_layout(const sense_desc& d) {
   Layout L{};
@@ -91,6 +98,8 @@ static sense_status validate_desc(const sense_desc* d) {
   for (int st : {d->maps_storage, d->kspace_storage})
     if (st < SENSE_C64 || st > SENSE_FP16X2) return fail(SENSE_ERR_INVALID, "unknown storage format");
   if (d->maps_shared != 0 && d->maps_shared != 1) return fail(SENSE_ERR_INVALID, "maps_shared must be 0 or 1");
+  if (d->kspace_compact != 0 && d->kspace_compact != 1)
+    return fail(SENSE_ERR_INVALID, "kspace_compact must be 0 or 1");
   if (d->ndim == 3 && !length_supported(d->nz))
     return fail(SENSE_ERR_UNSUPPORTED, "nz=" + std::to_string(d->nz) + " is not a supported transform length");
   if (!length_supported(d->ny))
@@ -199,7 +208,7 @@ sense_status check_solve_args(sense_plan p, const void* d_y, void* d_x, int32_t 
   if (!std::isfinite(lambda)) return fail(SENSE_ERR_INVALID, "lambda must be finite");
   const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
   const size_t xb = nvox * p->d.batch * sizeof(c32);
-  const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
+  const size_t yb = kspace_bytes(p);
   if (overlap(d_x, xb, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_x and d_y overlap");
   if (overlap(d_x, xb, p->mem, p->L.total) || overlap(d_y, yb, p->mem, p->L.total))
     return fail(SENSE_ERR_INVALID, "buffers overlap the plan workspace");
@@ -251,6 +260,7 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
     p->g.maps_bstride = d.maps_shared ? 0 : (long)(nvox * d.ncoils);
     p->g.maps_storage = d.maps_storage;
     p->g.kspace_storage = d.kspace_storage;
+    p->g.kspace_compact = d.kspace_compact;
 
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->mem), p->L.total);
     if (e != hipSuccess) {
@@ -338,7 +348,7 @@ sense_status sense_apply_E(sense_plan p, const void* d_x, void* d_y, void* strea
   if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
   const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
   const size_t xb = nvox * p->d.batch * sizeof(c32);
-  const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
+  const size_t yb = kspace_bytes(p);
   if (overlap(d_x, xb, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_x and d_y overlap");
   hipError_t e = launch_E(p->g, p->tb, p->maps, static_cast<const c32*>(d_x), p->at<c32>(p->L.work), d_y,
                           static_cast<hipStream_t>(stream));
@@ -352,7 +362,7 @@ sense_status sense_apply_EH(sense_plan p, const void* d_y, void* d_x, void* stre
   if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
   const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
   const size_t xb = nvox * p->d.batch * sizeof(c32);
-  const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
+  const size_t yb = kspace_bytes(p);
   if (overlap(d_x, xb, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_x and d_y overlap");
   hipError_t e = launch_EH(p->g, p->tb, p->maps, d_y, p->at<c32>(p->L.work), static_cast<c32*>(d_x),
                            p->vectors(nullptr).qpart, p->ngroups, static_cast<hipStream_t>(stream));
@@ -366,7 +376,7 @@ sense_status sense_apply_rss(sense_plan p, const void* d_y, float* d_img, void* 
   if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
   const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
   const size_t ob = nvox * p->d.batch * sizeof(float);
-  const size_t yb = nvox * p->d.batch * p->d.ncoils * storage_bytes(p->d.kspace_storage);
+  const size_t yb = kspace_bytes(p);
   if (overlap(d_img, ob, d_y, yb)) return fail(SENSE_ERR_INVALID, "d_img and d_y overlap");
   hipError_t e = launch_rss(p->g, p->tb, d_y, p->at<c32>(p->L.work), d_img, p->vectors(nullptr).qpart,
                             p->ngroups, static_cast<hipStream_t>(stream));

@@ -43,7 +43,7 @@ class Desc(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("nz", ctypes.c_int64), ("ncoils", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("maps_storage", ctypes.c_int32), ("kspace_storage", ctypes.c_int32),
-                ("maps_shared", ctypes.c_int32)]
+                ("maps_shared", ctypes.c_int32), ("kspace_compact", ctypes.c_int32)]
 
 
 class CgInfo(ctypes.Structure):
@@ -164,10 +164,12 @@ class Plan:
     maps: complex tensor on the GPU, [C][Ny][Nx] (shared by every batch
           element) or [B][C][Ny][Nx]; converted to ``maps_storage`` once.
     mask: uint8 array of Ny entries in centred order (DC at Ny // 2).
+    kspace_compact: k-space holds only the sampled lines, [B][C][L][Nx].
     """
 
     def __init__(self, maps: torch.Tensor, mask, batch: int = 1, maps_storage: str = "c64",
-                 kspace_storage: str = "c64", ndim: int | None = None, stream=None):
+                 kspace_storage: str = "c64", ndim: int | None = None, stream=None,
+                 kspace_compact: bool = False):
         if not maps.is_cuda:
             raise SenseError(1, "maps must be a GPU tensor")
         m = np.asarray(mask if not torch.is_tensor(mask) else mask.cpu().numpy())
@@ -200,8 +202,10 @@ class Plan:
         if m.size != self.ny * self.nz:
             raise SenseError(1, f"mask needs {self.ny * self.nz} entries")
         self.mask = m
+        self.kspace_compact = bool(kspace_compact)
+        self.nlines = int(np.count_nonzero(m))
         self.desc = Desc(ndim, self.nx, self.ny, self.nz, self.ncoils, self.batch, STORAGE[maps_storage],
-                         STORAGE[kspace_storage], int(shared))
+                         STORAGE[kspace_storage], int(shared), int(self.kspace_compact))
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().sense_plan_create(ctypes.byref(self.desc), _ptr(self._maps),
@@ -239,7 +243,16 @@ class Plan:
 
     @property
     def kspace_shape(self):
+        if self.kspace_compact:
+            return (self.batch, self.ncoils, self.nlines, self.nx)
         return (self.batch, self.ncoils) + self.grid
+
+    @property
+    def kspace_numel(self):
+        n = 1
+        for d in self.kspace_shape:
+            n *= d
+        return n
 
     @property
     def nvox(self):
@@ -254,10 +267,10 @@ class Plan:
 
     def _ksp(self, t: torch.Tensor, name: str):
         if self.kspace_storage == "c64":
-            ok = t.dtype == torch.complex64 and t.numel() == self.batch * self.ncoils * self.nvox
+            ok = t.dtype == torch.complex64 and t.numel() == self.kspace_numel
         else:
             dt = torch.bfloat16 if self.kspace_storage == "bf16" else torch.float16
-            ok = t.dtype == dt and t.numel() == 2 * self.batch * self.ncoils * self.nvox
+            ok = t.dtype == dt and t.numel() == 2 * self.kspace_numel
         if not ok or not t.is_contiguous() or t.device != self.device:
             raise SenseError(1, f"{name} must be contiguous k-space in {self.kspace_storage} storage")
         return t

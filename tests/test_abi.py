@@ -44,7 +44,7 @@ def test_version():
 
 def _desc(**kw):
     d = dict(ndim=2, nx=64, ny=64, nz=1, ncoils=4, batch=1, maps_storage=0, kspace_storage=0,
-             maps_shared=1)
+             maps_shared=1, kspace_compact=0)
     d.update(kw)
     return sense.Desc(**d)
 
@@ -77,6 +77,7 @@ def test_device_bytes():
     (dict(nz=2), 1, "nz"),
     (dict(kspace_storage=5), 1, "storage"),
     (dict(maps_shared=2), 1, "maps_shared"),
+    (dict(kspace_compact=3), 1, "kspace_compact"),
 ])
 def test_plan_create_rejects(kw, code, word):
     L = sense.lib()

@@ -62,6 +62,19 @@ def test_3d_rss_matches_oracle():
     assert err <= TOL_FP32
 
 
+def test_3d_compact_kspace_equals_full_grid():
+    maps, x, mask = _case3d(16, 32, 48, 3, 1, False, seed=41)
+    lines = np.flatnonzero(mask.ravel())
+    with sense.Plan(to_dev(maps), mask) as pf, sense.Plan(to_dev(maps), mask, kspace_compact=True) as pc:
+        assert pc.kspace_shape == (1, 3, len(lines), 48)
+        yf = pf.E(to_dev(x))
+        yc = pc.E(to_dev(x))
+        assert torch.equal(yc, yf.reshape(1, 3, 16 * 32, 48)[:, :, lines].contiguous())
+        assert torch.equal(pc.EH(yc), pf.EH(yf))
+        assert torch.equal(pc.rss(yc), pf.rss(yf))
+        assert torch.equal(pc.cg(yc, 4).x, pf.cg(yf, 4).x)
+
+
 def test_3d_ehe_ragged_readout():
     maps, x, mask = _case3d(8, 32, 40, 3, 2, False, seed=9)
     with sense.Plan(to_dev(maps), mask, batch=2) as plan:

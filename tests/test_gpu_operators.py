@@ -129,6 +129,24 @@ def test_rss_matches_oracle(ny, nx, nc, b, full):
     assert err <= TOL_FP32
 
 
+@pytest.mark.parametrize("storage", ["c64", "bf16"])
+def test_compact_kspace_equals_full_grid(storage):
+    """Compact k-space (sampled lines only) gives bitwise the values of the
+    full-grid path on the sampled lines: E, E^H, RSS and CG."""
+    ny, nx, nc, b = 128, 96, 4, 2
+    maps, x, mask = rand_case(ny, nx, nc, b, True, seed=31)
+    rows = np.flatnonzero(mask)
+    with sense.Plan(to_dev(maps), mask, batch=b, kspace_storage=storage) as pf, \
+            sense.Plan(to_dev(maps), mask, batch=b, kspace_storage=storage, kspace_compact=True) as pc:
+        assert pc.kspace_shape == (b, nc, len(rows), nx)
+        yf = pf.E(to_dev(x))
+        yc = pc.E(to_dev(x))
+        assert torch.equal(yc, yf[:, :, rows].contiguous())
+        assert torch.equal(pc.EH(yc), pf.EH(yf))
+        assert torch.equal(pc.rss(yc), pf.rss(yf))
+        assert torch.equal(pc.cg(yc, 6).x, pf.cg(yf, 6).x)
+
+
 def test_adjoint_identity_on_gpu():
     maps, x, mask = rand_case(128, 96, 4, 2, True, seed=9)
     yin = c64(synth.complex_normal((2, 4, 128, 96), 10))
