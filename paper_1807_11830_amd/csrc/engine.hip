@@ -54,6 +54,12 @@ struct sense_engine_s {
   hipEvent_t staged[2] = {nullptr, nullptr};
   int buf = 0;
   long steps = 0;
+  // the host runs at most kAhead steps ahead of the device, so a request
+  // admitted now starts behind at most kAhead queued steps
+  // (measured: 2 and 4 give the same latencies; without a bound the queue
+  // behind a new request grows with the load)
+  static constexpr int kAhead = 2;
+  hipEvent_t stepped[kAhead] = {};
 };
 
 static void engine_free(sense_engine e) {
@@ -65,6 +71,8 @@ static void engine_free(sense_engine e) {
     if (e->h_ehe[i]) (void)hipHostFree(e->h_ehe[i]);
     if (e->staged[i]) (void)hipEventDestroy(e->staged[i]);
   }
+  for (auto& ev : e->stepped)
+    if (ev) (void)hipEventDestroy(ev);
   if (e->d_ehe) (void)hipFree(e->d_ehe);
   if (e->st) (void)hipStreamDestroy(e->st);
   delete e;
@@ -87,6 +95,8 @@ sense_status sense_engine_create(size_t budget_bytes, int32_t max_slots, sense_e
     err = hipHostMalloc(reinterpret_cast<void**>(&e->h_ehe[i]), sizeof(EheParams) * max_slots, hipHostMallocDefault);
     if (err == hipSuccess) err = hipEventCreateWithFlags(&e->staged[i], hipEventDisableTiming);
   }
+  for (auto& ev : e->stepped)
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
   for (auto& s : e->slots)
     if (err == hipSuccess) err = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
   if (err != hipSuccess) {
@@ -168,38 +178,55 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
   if (n_running) *n_running = running;
   if (running == 0) return SENSE_OK;
 
-  // the staging buffer used two steps ago must have been consumed
-  const int b = e->buf;
-  hipError_t err = hipEventSynchronize(e->staged[b]);
-  EheParams* he = e->h_ehe[b];
-  int n = 0;
-  for (auto& g : groups)
+  hipError_t err = hipEventSynchronize(e->stepped[e->steps % sense_engine_s::kAhead]);
+  std::vector<EheParams> he;
+  he.reserve((size_t)running);
+  bool need_table = false;
+  for (auto& g : groups) {
+    need_table = need_table || g.second.size() > (size_t)kInlineProblems;
     for (int i : g.second) {
       Slot& sl = e->slots[(size_t)i];
       sense_plan p = sl.plan;
       const CgArgs cg = p->cg_args(sl.tol, nullptr, 0);
-      fill_ehe_cg_params(p->g, p->tb, p->maps, p->vectors(sl.x), sl.lambda, sl.k, cg, &he[n]);
-      ++n;
+      he.emplace_back();
+      fill_ehe_cg_params(p->g, p->tb, p->maps, p->vectors(sl.x), sl.lambda, sl.k, cg, &he.back());
     }
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(e->d_ehe, he, sizeof(EheParams) * n, hipMemcpyHostToDevice, e->st);
-  if (err == hipSuccess) err = hipEventRecord(e->staged[b], e->st);
-  e->buf ^= 1;
+  }
+  if (need_table && err == hipSuccess) {
+    // groups larger than a kernel-argument table read a device copy; the
+    // staging buffer used two steps ago must have been consumed
+    const int b = e->buf;
+    err = hipEventSynchronize(e->staged[b]);
+    if (err == hipSuccess) {
+      std::copy(he.begin(), he.end(), e->h_ehe[b]);
+      err = hipMemcpyAsync(e->d_ehe, e->h_ehe[b], sizeof(EheParams) * he.size(), hipMemcpyHostToDevice, e->st);
+    }
+    if (err == hipSuccess) err = hipEventRecord(e->staged[b], e->st);
+    e->buf ^= 1;
+  }
 
   int off = 0;
   for (auto& g : groups) {
     const int cnt = (int)g.second.size();
     int max_tiles = 0, max_groups = 1, max_ctiles = 0;
     for (int j = 0; j < cnt; ++j) {
-      const EheParams& P = he[off + j];
+      const EheParams& P = he[(size_t)(off + j)];
       max_tiles = std::max(max_tiles, P.ntiles);
       max_groups = std::max(max_groups, P.ngroups);
       if (P.ngroups > 1) max_ctiles = std::max(max_ctiles, P.part_tiles);
     }
     // the fused launch also finishes each problem's previous iteration
-    if (err == hipSuccess)
-      err = launch_ehe_table(g.first.first, g.first.second, e->d_ehe + off, cnt, max_tiles, max_groups, e->st);
-    if (err == hipSuccess && max_groups > 1) err = launch_combine_table(e->d_ehe + off, cnt, max_ctiles, e->st);
+    if (cnt <= kInlineProblems) {
+      EheInline t{};
+      std::copy(he.begin() + off, he.begin() + off + cnt, t.p);
+      if (err == hipSuccess)
+        err = launch_ehe_inline(g.first.first, g.first.second, t, cnt, max_tiles, max_groups, e->st);
+      if (err == hipSuccess && max_groups > 1) err = launch_combine_inline(t, cnt, max_ctiles, e->st);
+    } else {
+      if (err == hipSuccess)
+        err = launch_ehe_table(g.first.first, g.first.second, e->d_ehe + off, cnt, max_tiles, max_groups, e->st);
+      if (err == hipSuccess && max_groups > 1) err = launch_combine_table(e->d_ehe + off, cnt, max_ctiles, e->st);
+    }
     off += cnt;
   }
   for (auto& g : groups)
@@ -211,6 +238,7 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
         sl.finishing = true;
       }
     }
+  if (err == hipSuccess) err = hipEventRecord(e->stepped[e->steps % sense_engine_s::kAhead], e->st);
   ++e->steps;
   return err == hipSuccess ? SENSE_OK : device_fail(err, "sense_engine_step");
 }

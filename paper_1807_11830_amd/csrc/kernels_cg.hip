@@ -289,6 +289,19 @@ __global__ void __launch_bounds__(CG_NT) combine_table_kernel(const EheParams* _
   combine_body(P, 0, blockIdx.x, true);
 }
 
+__global__ void __launch_bounds__(CG_NT) combine_inline_kernel(EheInline table) {
+  const EheParams& P = table.p[blockIdx.y];
+  if (P.ngroups < 2) return;
+  combine_body(P, 0, blockIdx.x, true);
+}
+
+hipError_t launch_combine_inline(const EheInline& table, int nproblems, int max_tiles, hipStream_t st) {
+  if (nproblems > kInlineProblems) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(combine_inline_kernel, dim3((unsigned)max_tiles, (unsigned)nproblems), dim3(CG_NT), 0, st,
+                     table);
+  return hipGetLastError();
+}
+
 hipError_t launch_combine(const EheParams& P, int batch, bool cg, hipStream_t st) {
   dim3 grid((unsigned)cg_tiles(P.nvox), (unsigned)batch);
   if (cg) hipLaunchKernelGGL(combine_kernel<true>, grid, dim3(CG_NT), 0, st, P);

@@ -254,6 +254,14 @@ __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX)
   ehe2d_body<N, ST, true>(P, blockIdx.x, 0, blockIdx.z);
 }
 
+// The same with the table passed by value in the kernel arguments.
+template <int N, int ST>
+__global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX) ehe2d_inline_kernel(EheInline table) {
+  const EheParams& P = table.p[blockIdx.y];
+  if ((long)blockIdx.x >= (long)P.ntiles || (int)blockIdx.z >= P.ngroups) return;
+  ehe2d_body<N, ST, true>(P, blockIdx.x, 0, blockIdx.z);
+}
+
 int ehe_tile_width(long ny) {
   int tx = 0;
   dispatch_length(ny, [&](auto nc) {
@@ -344,6 +352,25 @@ hipError_t launch_ehe_table(long ny, int maps_storage, const EheParams* d_table,
       case ST_C64: hipLaunchKernelGGL((ehe2d_table_kernel<N, ST_C64>), grid, block, 0, st, d_table); break;
       case ST_BF16: hipLaunchKernelGGL((ehe2d_table_kernel<N, ST_BF16>), grid, block, 0, st, d_table); break;
       case ST_FP16: hipLaunchKernelGGL((ehe2d_table_kernel<N, ST_FP16>), grid, block, 0, st, d_table); break;
+      default: return;
+    }
+    err = hipGetLastError();
+  });
+  return err;
+}
+
+hipError_t launch_ehe_inline(long ny, int maps_storage, const EheInline& table, int nproblems, int max_tiles,
+                             int max_groups, hipStream_t st) {
+  if (nproblems > kInlineProblems) return hipErrorInvalidValue;
+  hipError_t err = hipErrorInvalidValue;
+  dispatch_length(ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    dim3 grid((unsigned)max_tiles, (unsigned)nproblems, (unsigned)max_groups);
+    dim3 block(EheLen<N>::T * EheLen<N>::TX);
+    switch (maps_storage) {
+      case ST_C64: hipLaunchKernelGGL((ehe2d_inline_kernel<N, ST_C64>), grid, block, 0, st, table); break;
+      case ST_BF16: hipLaunchKernelGGL((ehe2d_inline_kernel<N, ST_BF16>), grid, block, 0, st, table); break;
+      case ST_FP16: hipLaunchKernelGGL((ehe2d_inline_kernel<N, ST_FP16>), grid, block, 0, st, table); break;
       default: return;
     }
     err = hipGetLastError();

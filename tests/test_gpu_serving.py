@@ -44,6 +44,23 @@ def test_alone_equals_mixed_bitwise():
         assert torch.equal(r.result, alone[r.id][0])
 
 
+def test_large_group_uses_device_table_bitwise():
+    """20 same-size requests in flight: one group larger than a kernel-argument
+    table, so the step reads a device copy of the table; results are still
+    bitwise those of the plain solve."""
+    bank = InputBank()
+    reqs = [Request(i, 0.0, 128, 8, 2 + i % 3, 10) for i in range(20)]
+    bank.prepare(reqs)
+    alone = {r.id: _alone(bank, r) for r in reqs}
+    ex = EngineExecutor(bank, budget_bytes=8 << 30, max_slots=32)
+    st = Scheduler(ex).run(reqs)
+    ex.close()
+    log(f"large group: max in flight {st.max_inflight}")
+    assert st.max_inflight > 16
+    for r in reqs:
+        assert torch.equal(r.result, alone[r.id][0]), r
+
+
 def test_mixed_request_matches_oracle():
     bank = InputBank()
     reqs = make_requests(10, rate=5000.0, iters=10, sizes=(128, 192), coils=(8,), accels=(2, 3))
