@@ -42,6 +42,20 @@ struct LineView {
   __device__ __forceinline__ c32& at(int p) const { return base[p * PS]; }
 };
 
+// A line stored contiguously with one pad element after every 16: Stockham
+// writes at stride 16 (the radix-16 and radix-16-span patterns) would
+// otherwise land all 16 threads of a line on the same LDS bank pair.
+struct PadLineView {
+  c32* base;
+  __device__ __forceinline__ c32& at(int p) const { return base[p + (p >> 4)]; }
+};
+// Elements of one padded line of length N (plus one, so consecutive lines
+// start on different banks).
+template <int N>
+constexpr int padded_line() {
+  return N + N / 16 + 1;
+}
+
 // Twiddle sources.  A stage of span NS and radix R multiplies input r of
 // butterfly jb (m-th of the thread) by exp(DIR 2 pi i r (jb mod NS) / (NS R)),
 // read from tw[e] = exp(-2 pi i e / N) at e = (jb mod NS) * r * N / (NS R).

@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
   constexpr int T = Len<N>::T;
   constexpr int E = Len<N>::E;
   constexpr int TR = ROW_NT / T;
-  constexpr int LDL = N + 1;
+  constexpr int LDL = padded_line<N>();
   using Rad = typename Len<N>::R;
   __shared__ c32 buf[TR * LDL];
   __shared__ c32 tw[N];
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
 #pragma unroll
   for (int j = 0; j < E; ++j) v[j] = valid ? cscale(load_c<ST_IN>(in, t + T * j), sgn) : c32{0.f, 0.f};
   __syncthreads();
-  LineView<1> lv{&buf[l * LDL]};
+  PadLineView lv{&buf[l * LDL]};
   fft_line<N, T, DIR>(v, t, TwTable{tw}, lv, Rad{});
   if (valid) {
     TO* out = static_cast<TO*>(P.out) + off_out;
