@@ -330,7 +330,8 @@ def run_autograd3d(args):
 
         dt = timed(fwd_bwd)
         dt_loss = timed(loss_step)
-    # the same pair with compact k-space (sampled (ky, kz) lines only)
+    # the same pair with compact k-space (sampled (ky, kz) lines only), and
+    # 3D CG-SENSE iterations on the compact data
     with sense.Plan(maps, mask, kspace_compact=True) as plan:
         g = plan.E(x_true)
 
@@ -340,9 +341,19 @@ def run_autograd3d(args):
 
         dt_c = timed(fwd_bwd_compact)
         nlines = plan.nlines
+        xs = torch.empty_like(x_true)
+        K = 10
+        plan.cg(g, K, out=xs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            plan.cg(g, K, out=xs, sync=False)
+        torch.cuda.synchronize()
+        dt_cg = (time.perf_counter() - t0) / 3
     nvox = nx * ny * nz
     nbytes = 8 * nvox * (2 * C + 1) * 2
     nbytes_c = 2 * (8 * nvox * (C + 1) + 8 * C * nlines * nx)
+    log(f"autograd3d: 3D CG {dt_cg * 1e3:.2f} ms per {K}-iteration solve (compact k-space)")
     log(f"autograd3d: fwd+bwd {dt * 1e3:.2f} ms ({nbytes / dt / 1e9:.0f} GB/s algorithmic), "
         f"loss step {dt_loss * 1e3:.2f} ms, compact k-space fwd+bwd {dt_c * 1e3:.2f} ms "
         f"({nbytes_c / dt_c / 1e9:.0f} GB/s algorithmic)")
@@ -353,7 +364,8 @@ def run_autograd3d(args):
                       "algorithmic_bytes": nbytes, "achieved_gbs": nbytes / dt / 1e9,
                       "loss_step_ms": dt_loss * 1e3,
                       "compact_kspace": {"ms_per_step": dt_c * 1e3, "algorithmic_bytes": nbytes_c,
-                                         "achieved_gbs": nbytes_c / dt_c / 1e9}}), flush=True)
+                                         "achieved_gbs": nbytes_c / dt_c / 1e9},
+                      "cg3d": {"iters": K, "ms_per_solve": dt_cg * 1e3}}), flush=True)
 
 
 def run_cgsense(args):

@@ -116,16 +116,19 @@ __global__ void __launch_bounds__(CG_NT) cg_update_kernel(c32* __restrict__ x, c
   cg_update_body(x, r, p, q, nvox, cg, blockIdx.y, blockIdx.x);
 }
 
-__global__ void cg_finish_kernel(CgArgs cg, CgInfo* info, CgInfo* info2) {
+__global__ void __launch_bounds__(64) cg_finish_kernel(CgArgs cg, CgInfo* info, CgInfo* info2) {
   const int b = blockIdx.x;
-  if (threadIdx.x != 0) return;
   CgState* st = cg.state + b;
+  const int status0 = st->status;
+  // every lane takes part in the ordered sum; lane 0 publishes
+  const double rho_all = status0 == CG_RUNNING ? ordered_sum(cg.rr_part + (long)b * cg.rr_tiles, cg.rr_tiles) : 0.0;
+  if (threadIdx.x != 0) return;
   const int k = st->iter;
-  int status = st->status;
+  int status = status0;
   double rho0 = st->rho0;
   double rho_final;
   if (status == CG_RUNNING) {
-    const double rho = ordered_sum(cg.rr_part + (long)b * cg.rr_tiles, cg.rr_tiles);
+    const double rho = rho_all;
     if (k == 0) rho0 = rho;
     if (cg.rho_hist && k < cg.hist_len) cg.rho_hist[(long)b * cg.hist_len + k] = rho;
     if (!finite64(rho)) status = CG_NONFINITE;

@@ -34,11 +34,20 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   }
 }
 
-// Sum of n partials in index order (same result in every block).
+// Sum of n partials in a fixed order, the same in every block: in index
+// order for n <= 64; above that lane l sums p[l], p[l + 64], ... in index
+// order and the 64 lane sums go through the fixed butterfly.  All 64 lanes
+// of the calling wavefront must be active.
 __device__ __forceinline__ double ordered_sum(const double* __restrict__ p, int n) {
+  if (n <= 64) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += p[i];
+    return s;
+  }
+  const int lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += p[i];
-  return s;
+  for (int i = lane; i < n; i += 64) s += p[i];
+  return wave_sum(s);
 }
 
 __device__ __forceinline__ bool finite64(double v) { return __builtin_isfinite(v); }
