@@ -2,7 +2,10 @@
 // (base, size) lives in scalar registers; each access takes a per-thread
 // byte offset (one VGPR) plus a wavefront-uniform byte offset (SGPR), so the
 // strided row accesses of a column need no 64-bit per-access address math.
-// Every offset used here stays inside the resource's range.
+// Every offset used here stays inside the resource's range, except
+// kBufOOB: the buffer unit range-checks raw accesses against the resource
+// size and returns zero for an out-of-range load without a memory request,
+// so a load at kBufOOB is a branch-free masked load.
 #pragma once
 
 #include "cplx.hpp"
@@ -11,6 +14,10 @@ namespace sense {
 
 // Word 3 of a raw gfx9 buffer descriptor (32-bit data format, no swizzle).
 constexpr int kBufWord3 = 0x00020000;
+
+// Per-thread byte offset beyond every resource made here (one image or coil
+// image is below 2^31 bytes, which plan validation enforces).
+constexpr uint32_t kBufOOB = 0x80000000u;
 
 struct Buf {
   __amdgpu_buffer_rsrc_t r;

@@ -153,6 +153,7 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
   using Rad = typename Len<N>::R;
   __shared__ c32 buf[N * TX];
   __shared__ c32 tw[N];
+  __shared__ uint8_t msk[N];  // the mask along this pass's line
   __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
 
   const int tid = threadIdx.x, cx = tid % TX, t = tid / TX;
@@ -167,10 +168,14 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
   const uint32_t voff = lbase + (uint32_t)t * es;
   const uint32_t rstep = (uint32_t)T * es;
   const uint32_t vbytes = (uint32_t)(nvox * 8);
-  auto mask_at = [&](int k) -> bool {
-    return AXIS == 1 ? P.mask[pl * ny + k] != 0 : P.mask[(long)k * ny + pl] != 0;
-  };
-  for (int i = tid; i < N; i += NT) tw[i] = P.tw[i];
+  // The mask along the line is staged in LDS once, so masked loads and
+  // stores never wait on a global byte load (which would also wait for
+  // every data load issued before it).
+  for (int i = tid; i < N; i += NT) {
+    tw[i] = P.tw[i];
+    msk[i] = P.mask ? (AXIS == 1 ? P.mask[pl * ny + i] : P.mask[(long)i * ny + pl]) : 1;
+  }
+  auto mask_at = [&](int k) -> bool { return msk[k] != 0; };
   __syncthreads();
 
   using SType = typename StorageT<ST>::T;
@@ -195,11 +200,12 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
       const Buf bw = make_buf(P.src + bc * nvox, vbytes);
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        // masked-out lines are not read at all (no memory request)
+        // masked-out lines are not read at all: an out-of-range offset
+        // returns zero without a memory request, and without a branch that
+        // would serialise the loads
         const bool on = MODE == CM_ADJ && P.mask_load ? mask_at(t + T * j) : true;
-        c32 v = {0.f, 0.f};
-        if (on) v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
-        u[j] = cscale(v, sgn);
+        const uint32_t o = on ? (voff + (uint32_t)j * rstep) * 8u : kBufOOB;
+        u[j] = cscale(buf_load_c64(bw, o, 0), sgn);
       }
     }
     if constexpr (MODE == CM_ADJ) {
@@ -240,9 +246,8 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const bool on = P.mask_load ? mask_at(t + T * j) : true;
-        c32 v = {0.f, 0.f};
-        if (on) v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
-        u[j] = cscale(v, sgn);
+        const uint32_t o = on ? (voff + (uint32_t)j * rstep) * 8u : kBufOOB;
+        u[j] = cscale(buf_load_c64(bw, o, 0), sgn);
       }
       // the coil's maps are loaded before the transform so their latency
       // hides behind it (measured 16% faster for 256^2 x 12 coils x 160
@@ -298,6 +303,7 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) rss_colpass
   using Rad = typename Len<N>::R;
   __shared__ c32 buf[N * TX];
   __shared__ c32 tw[N];
+  __shared__ uint8_t msk[N];
 
   const int tid = threadIdx.x, cx = tid % TX, t = tid / TX;
   const long nx = P.nx, ny = P.ny;
@@ -313,7 +319,10 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) rss_colpass
   const uint32_t voff = (uint32_t)(pl * ny * nx) + xl + (uint32_t)t * (uint32_t)nx;
   const uint32_t rstep = (uint32_t)T * (uint32_t)nx;
   const uint32_t vbytes = (uint32_t)(nvox * 8);
-  for (int i = tid; i < N; i += NT) tw[i] = P.tw[i];
+  for (int i = tid; i < N; i += NT) {
+    tw[i] = P.tw[i];
+    msk[i] = P.mask_load ? P.mask[pl * ny + i] : 1;
+  }
   __syncthreads();
   const float sgn = (t & 1) ? -1.f : 1.f;  // output sign is irrelevant to |u|^2
   LineView<TX> lv{&buf[cx]};
@@ -326,10 +335,8 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) rss_colpass
     c32 u[E];
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const bool on = P.mask_load ? P.mask[pl * ny + t + T * j] != 0 : true;
-      c32 v = {0.f, 0.f};
-      if (on) v = buf_load_c64(bw, (voff + (uint32_t)j * rstep) * 8u, 0);
-      u[j] = cscale(v, sgn);
+      const uint32_t o = msk[t + T * j] ? (voff + (uint32_t)j * rstep) * 8u : kBufOOB;
+      u[j] = cscale(buf_load_c64(bw, o, 0), sgn);
     }
     fft_line<N, T, +1>(u, t, twt, lv, Rad{});
 #pragma unroll
