@@ -76,7 +76,9 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
   const float sgn = (t & 1) ? -1.f : 1.f;
   c32 v[E];
 #pragma unroll
-  for (int j = 0; j < E; ++j) v[j] = valid ? cscale(load_c<ST_IN>(in, t + T * j), sgn) : c32{0.f, 0.f};
+  // unconditional loads (a line past the end reads the buffer's first line,
+  // never stored): a per-element branch would serialise the loads
+  for (int j = 0; j < E; ++j) v[j] = cscale(load_c<ST_IN>(in, t + T * j), sgn);
   __syncthreads();
   PadLineView lv{&buf[l * LDL]};
   fft_line<N, T, DIR>(v, t, TwTable{tw}, lv, Rad{});
@@ -270,17 +272,18 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
     }
     const Buf bd = make_buf(P.dst + b * nvox, vbytes);
     double eta = 0.0;
-    [[maybe_unused]] Buf bp;
-    if (P.addp) bp = make_buf(P.addp + b * nvox, vbytes);
+    // p for lambda p and Re<p, q>: all loads first (an out-of-range offset
+    // when there is no p), so no wait falls between two of them
+    const Buf bp = make_buf(P.addp ? P.addp + b * nvox : P.dst, vbytes);
+    c32 pv[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) pv[j] = buf_load_c64(bp, P.addp ? (voff + (uint32_t)j * rstep) * 8u : kBufOOB, 0);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const uint32_t o = (voff + (uint32_t)j * rstep) * 8u;
       c32 qq = cscale(acc[j], P.scale);
-      if (P.addp) {
-        const c32 pv = buf_load_c64(bp, o, 0);
-        qq = {qq.re + P.lambda * pv.re, qq.im + P.lambda * pv.im};
-        eta += (double)pv.re * (double)qq.re + (double)pv.im * (double)qq.im;
-      }
+      qq = {qq.re + P.lambda * pv[j].re, qq.im + P.lambda * pv[j].im};
+      eta += (double)pv[j].re * (double)qq.re + (double)pv[j].im * (double)qq.im;
       if (valid) buf_store_c64(bd, qq, o, 0);
     }
     if (P.eta_part) {

@@ -46,7 +46,14 @@ __device__ __forceinline__ double ordered_sum(const double* __restrict__ p, int 
   }
   const int lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int i = lane; i < n; i += 64) s += p[i];
+  // eight loads in flight per lane, added in index order
+  for (int i0 = lane; i0 < n; i0 += 64 * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = i0 + 64 * u < n ? p[i0 + 64 * u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
   return wave_sum(s);
 }
 
