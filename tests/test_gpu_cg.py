@@ -84,6 +84,30 @@ def test_cg_coil_groups(G):
     assert torch.equal(r1, r2)
 
 
+@pytest.mark.parametrize("G", [1, 2])
+def test_cg_tikhonov_matches_oracle(G):
+    """Regularised CG-SENSE (lambda = 0.05) on the 64x64 / 4-coil problem,
+    with and without coil groups, against the oracle's CG on E^H E + lambda I;
+    also the rho history and a tolerance stop."""
+    w = synth.SMALL_64
+    imgs, maps, mask, y = _problem(w)
+    lam = 0.05
+    xo, it, st, hist = oracle.cg(y, maps, mask, w.iters, lam=lam)
+    xt, itt, stt, _ = oracle.cg(y, maps, mask, 50, tol=1e-3, lam=lam)
+    with sense.Plan(to_dev(maps), mask, batch=1) as plan:
+        plan.set_coil_groups(G)
+        res = plan.cg(to_dev(y), w.iters, lam=lam, history=True)
+        rt = plan.cg(to_dev(y), 50, tol=1e-3, lam=lam)
+    err = rel_l2(to_host(res.x), xo)
+    log(f"64x64 CG lambda={lam} G={G} rel-L2 {err:.3e}; tol stop at {rt.iters[0]} (oracle {itt[0]})")
+    assert err <= TOL_FP32
+    assert np.allclose(res.rho_hist.cpu().numpy()[0, :6], hist[0, :6], rtol=1e-5)
+    assert rt.status[0] == sense.CONVERGED == stt[0]
+    assert abs(int(rt.iters[0]) - int(itt[0])) <= 1
+    if int(rt.iters[0]) == int(itt[0]):  # the same number of updates
+        assert rel_l2(to_host(rt.x), xt) <= TOL_FP32
+
+
 def test_cg_batch_per_slice_maps():
     w = synth.SMALL_64
     imgs, maps, mask, y = _problem(w, batch=3, per_slice_maps=True)

@@ -61,6 +61,30 @@ def test_large_group_uses_device_table_bitwise():
         assert torch.equal(r.result, alone[r.id][0]), r
 
 
+def test_mixed_storage_groups_bitwise():
+    """Plans with complex64 and BF16 maps of the same size form separate
+    groups in a step; each result is bitwise its plain solve."""
+    bank = InputBank()
+    reqs = [Request(i, 0.0, 192, 8, 3, 8) for i in range(6)]
+    bank.prepare(reqs)
+    maps, mask = bank.coil_maps(192, 8), bank.mask(192, 3)
+    y = bank.kspace(192, 8, 3)
+    plans = [sense.Plan(maps, mask, maps_storage="bf16" if i % 2 else "c64") for i in range(6)]
+    outs = [torch.empty((1, 192, 192), dtype=torch.complex64, device="cuda:0") for _ in range(6)]
+    with sense.Engine(budget_bytes=1 << 32, max_slots=8) as eng:
+        for i, p in enumerate(plans):
+            assert eng.admit(p, y, outs[i], 8) == i
+        done = []
+        while len(done) < 6:
+            eng.step()
+            done += eng.poll()
+    for i, p in enumerate(plans):
+        ref = p.cg(y, 8).x
+        assert torch.equal(outs[i], ref), i
+        p.close()
+    assert not torch.equal(outs[0], outs[1])  # the storages really differ
+
+
 def test_mixed_request_matches_oracle():
     bank = InputBank()
     reqs = make_requests(10, rate=5000.0, iters=10, sizes=(128, 192), coils=(8,), accels=(2, 3))
