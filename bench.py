@@ -107,16 +107,17 @@ def cpu_baseline(w, maps0, mask, y0, target_s):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     maps0 = maps0.astype(np.complex128)
     y0 = y0.astype(np.complex128)[None]
-    t0 = time.perf_counter()
-    oracle.A(oracle.EH(y0, maps0, mask), maps0, mask)
-    t_a = time.perf_counter() - t0
-    # whole solves of the workload's iteration count, repeated to ~target_s
+    oracle.A(oracle.EH(y0, maps0, mask), maps0, mask)  # warm-up (library load, threads)
+    # whole solves of the workload's iteration count, repeated until ~target_s
     k = w.iters
-    reps = int(max(1, round(target_s / max(t_a * (k + 1), 1e-3))))
+    reps = 0
     t0 = time.perf_counter()
-    for _ in range(reps):
+    while True:
         oracle.cg(y0, maps0, mask, k)
-    dt = time.perf_counter() - t0
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= target_s:
+            break
     return dict(value=reps * k / dt, unit="applies/s", cores=min(threads, w.ncoils), kind="oracle",
                 sample=f"1 slice {w.n}x{w.n}, {w.ncoils} coils, {reps} x (E^H y + {k} CG iterations), "
                        f"E^H E composed as E^H(E p) in fp64, {min(threads, w.ncoils)} OpenMP threads "
