@@ -70,7 +70,7 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--maps-storage", default="c64", choices=["c64", "bf16", "fp16"])
-    ap.add_argument("--workload", default="cgsense", choices=["cgsense", "serving", "precision", "autograd3d", "paper"],
+    ap.add_argument("--workload", default="cgsense", choices=["cgsense", "serving", "precision", "autograd3d", "paper", "small"],
                     help="cgsense (default, the metric's workload); the others print their own line")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -131,7 +131,7 @@ def main():
               "(slices are independent: shard the batch across processes instead)", file=sys.stderr)
         sys.exit(2)
     {"cgsense": run_cgsense, "serving": run_serving, "precision": run_precision,
-     "autograd3d": run_autograd3d, "paper": run_paper}[args.workload](args)
+     "autograd3d": run_autograd3d, "paper": run_paper, "small": run_small}[args.workload](args)
 
 
 def run_serving(args):
@@ -245,6 +245,43 @@ def run_precision(args):
                       "value": out["bf16"]["applies_per_s"], "unit": "applies/s", "n_gpus": 1,
                       "higher_is_better": True, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": w.name, "slices": B, "iters": K}, "variants": out}), flush=True)
+
+
+def run_small(args):
+    """One 64x64 slice, 4 coils, 20 CG iterations: the latency of a single
+    solve replayed from its captured HIP graph and launched eagerly, and
+    replayed with the coils forced into the workspace's fill split."""
+    import torch
+
+    from paper_1807_11830_amd import sense, synth
+
+    w = synth.SMALL_64
+    dev = torch.device("cuda:0")
+    imgs, maps, mask = synth.slice_inputs(w, 1)
+    maps_t = torch.from_numpy(maps.astype(np.complex64)).to(dev)
+    out = {}
+    with sense.Plan(maps_t, mask) as plan:
+        y = plan.E(torch.from_numpy(imgs.astype(np.complex64)).to(dev))
+        x = torch.empty((1, w.n, w.n), dtype=torch.complex64, device=dev)
+        gdef, gmax = plan.coil_groups()
+        # the default (one coil group at this size) and the fill split forced
+        for mode in ("graph", "eager", f"graph_G{gmax}"):
+            plan.set_graphs(mode != "eager")
+            plan.set_coil_groups(gmax if mode.endswith(f"_G{gmax}") else gdef)
+            for _ in range(20):
+                plan.cg(y, w.iters, out=x, sync=False)
+            torch.cuda.synchronize()
+            reps = 200
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.cg(y, w.iters, out=x, sync=False)
+            torch.cuda.synchronize()
+            out[mode] = (time.perf_counter() - t0) / reps * 1e6
+            log(f"small: {mode} {out[mode]:.1f} us per solve")
+    print(json.dumps({"metric": "CG-SENSE solve latency (64x64, 4 coils, 20 iterations)", "value": out["graph"],
+                      "unit": "us", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
+                      "data": "synthetic", "config": {"workload": w.name},
+                      "us_per_solve": out}), flush=True)
 
 
 def run_paper(args):
@@ -394,7 +431,8 @@ def run_cgsense(args):
     for _ in range(args.warmup):
         plan.cg(y, K, out=x, sync=False)
     torch.cuda.synchronize()
-    plan.set_profiling(True)
+    # the timed steps run the production path: each solve replays its
+    # captured HIP graph
     log(f"bench: timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -402,6 +440,12 @@ def run_cgsense(args):
         plan.cg(y, K, out=x, sync=False)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # per-launch times of the fused kernel: HIP events around every launch
+    # on the plan's stream (eager launches) for a few more solves
+    plan.set_profiling(True)
+    for _ in range(max(1, min(args.steps, 5))):
+        plan.cg(y, K, out=x, sync=False)
+    torch.cuda.synchronize()
     n_l, ms_l = plan.profile()
     plan.set_profiling(False)
     res = plan.cg(y, K, out=x)

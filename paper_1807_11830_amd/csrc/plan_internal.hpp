@@ -17,7 +17,8 @@ struct Layout {
   size_t state, eta_part, rr_part, part4, info;
   size_t total;
   int eta_tiles, rr_tiles;
-  int ngroups;  // coil groups the workspace holds (the automatic choice)
+  int ngroups;   // coil groups the workspace holds (the fill split)
+  int dgroups;   // the plan's default (ngroups, or 1 for small slices)
 };
 
 sense_status fail(sense_status s, const std::string& msg);
