@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # runs recorded under profiles/; it is reported only while the kernel sources
 # still hash to what was measured.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cgsense_256x256_c12_b160_k30.traffic.json")
-EHE_SOURCES = ["kernels_ehe.hip", "fft_engine.hpp", "dft_small.hpp", "cplx.hpp", "bufio.hpp",
+EHE_SOURCES = ["kernels_ehe.hip", "fft_engine.hpp", "dft_small.hpp", "cplx.hpp", "bufio.hpp", "xcd.hpp",
                "lengths.hpp", "reduce.hpp", "kernels.hpp", "cg_scalar.hpp"]
 
 

@@ -24,6 +24,7 @@
 #include "kernels.hpp"
 #include "lengths.hpp"
 #include "reduce.hpp"
+#include "xcd.hpp"
 
 #include <cmath>
 
@@ -57,7 +58,7 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
   const int tid = threadIdx.x;
   const int t = tid % T;
   const int l = tid / T;
-  const long L = (long)blockIdx.x * TR + l;
+  const long L = (long)xcd_order(blockIdx.x, gridDim.x) * TR + l;
   const bool valid = L < P.lines;
   for (int i = tid; i < N; i += ROW_NT) tw[i] = P.tw[i];
 
@@ -160,10 +161,11 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
 
   const int tid = threadIdx.x, cx = tid % TX, t = tid / TX;
   const long nx = P.nx, ny = P.ny;
-  const long x = (long)blockIdx.x * TX + cx;
+  const BlockId id = xcd_block();
+  const long x = (long)id.x * TX + cx;
   const bool valid = x < nx;
   const uint32_t xl = (uint32_t)(valid ? x : nx - 1);
-  const long pl = blockIdx.y;  // z for AXIS 1, y for AXIS 2
+  const long pl = id.y;  // z for AXIS 1, y for AXIS 2
   const long nvox = nx * ny * P.nz;
   const uint32_t es = (uint32_t)(AXIS == 1 ? nx : nx * ny);
   const uint32_t lbase = (uint32_t)(AXIS == 1 ? pl * ny * nx : pl * nx) + xl;
@@ -186,7 +188,7 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
   const TwTable twt{tw};
 
   if constexpr (MODE != CM_ADJ_COIL) {
-    const long bc = blockIdx.z;
+    const long bc = id.z;
     const long b = bc / P.ncoils, c = bc % P.ncoils;
     c32 u[E];
     if constexpr (MODE == CM_FWD_COIL) {
@@ -234,8 +236,8 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
     }
   } else {
     const int G = P.ngroups;
-    const long b = blockIdx.z / G;
-    const int grp = (int)(blockIdx.z % G);
+    const long b = id.z / G;
+    const int grp = (int)(id.z % G);
     const int c0 = (int)((long)grp * P.ncoils / G), c1 = (int)((long)(grp + 1) * P.ncoils / G);
     c32 acc[E];
 #pragma unroll
@@ -289,7 +291,7 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
     if (P.eta_part) {
       if (!valid) eta = 0.0;
       const double tot = block_sum<NT>(eta, red);
-      if (tid == 0) P.eta_part[b * (long)gridDim.x * gridDim.y + (long)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+      if (tid == 0) P.eta_part[b * (long)gridDim.x * gridDim.y + (long)id.y * gridDim.x + id.x] = tot;
     }
   }
 }
@@ -310,13 +312,14 @@ __global__ void __launch_bounds__(Len<N>::T * col_tile<Len<N>::T>()) rss_colpass
 
   const int tid = threadIdx.x, cx = tid % TX, t = tid / TX;
   const long nx = P.nx, ny = P.ny;
-  const long x = (long)blockIdx.x * TX + cx;
+  const BlockId id = xcd_block();
+  const long x = (long)id.x * TX + cx;
   const bool valid = x < nx;
   const uint32_t xl = (uint32_t)(valid ? x : nx - 1);
-  const long pl = blockIdx.y;  // z plane
+  const long pl = id.y;  // z plane
   const int G = P.ngroups;
-  const long b = blockIdx.z / G;
-  const int grp = (int)(blockIdx.z % G);
+  const long b = id.z / G;
+  const int grp = (int)(id.z % G);
   const int c0 = (int)((long)grp * P.ncoils / G), c1 = (int)((long)(grp + 1) * P.ncoils / G);
   const long nvox = nx * ny * P.nz;
   const uint32_t voff = (uint32_t)(pl * ny * nx) + xl + (uint32_t)t * (uint32_t)nx;

@@ -24,6 +24,7 @@
 #include "kernels.hpp"
 #include "lengths.hpp"
 #include "reduce.hpp"
+#include "xcd.hpp"
 
 namespace sense {
 
@@ -239,7 +240,8 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
 
 template <int N, int ST, bool CG>
 __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX) ehe2d_kernel(EheParams P) {
-  ehe2d_body<N, ST, CG>(P, blockIdx.x, blockIdx.y, blockIdx.z);
+  const BlockId id = xcd_block();
+  ehe2d_body<N, ST, CG>(P, (int)id.x, (int)id.y, (int)id.z);
 }
 
 // Batched CG launch over many independent single-slice problems of the same
