@@ -40,6 +40,42 @@ __device__ __forceinline__ void buf_store_c64(Buf b, c32 v, uint32_t voff, uint3
                                         b.r, (int)voff, (int)soff, 0);
 }
 
+// 16-byte chunks copied from global memory straight into LDS
+// (buffer_load_dwordx4 ... lds).  Lane l of the wave writes bytes
+// [16 l, 16 l + 16) of the LDS window at lds_addr (an LDS byte address, the
+// same for every lane), reading resource offset voff + soff; the access is
+// range-checked like any buffer access.  It is issued from inline assembly:
+// the compiler cannot tell the copy's LDS window from other LDS arrays and
+// would otherwise wait for the copy before every later LDS read.  The caller
+// therefore waits itself (s_waitcnt vmcnt(0)) before reading the window, and
+// must not refill a window before its own reads of it have completed
+// (s_waitcnt lgkmcnt(0)).  M0 carries the LDS address and is restored
+// after the copy is issued.
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4i32 make_rsrc(const void* base, uint32_t bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(base);
+  return {(int)(uint32_t)a, (int)((uint32_t)(a >> 32) & 0xffffu), (int)bytes, kBufWord3};
+}
+
+__device__ __forceinline__ void buf_load_lds16(v4i32 rsrc, uint32_t lds_addr, uint32_t voff, uint32_t soff) {
+  uint32_t saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "buffer_load_dwordx4 %2, %3, %4 offen lds\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "s"(lds_addr), "v"(voff), "s"(rsrc), "s"(soff)
+      : "memory");
+}
+
+// LDS byte address of a pointer into a __shared__ array.
+template <class T>
+__device__ __forceinline__ uint32_t lds_address(T* p) {
+  return (uint32_t)reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) T*)p);
+}
+
 // Complex value in storage ST at (voff + soff) element offsets, converted to fp32.
 template <int ST>
 __device__ __forceinline__ c32 buf_load_st(Buf b, uint32_t vi, uint32_t si) {

@@ -17,6 +17,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -167,11 +168,16 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != e->device)
     return fail(SENSE_ERR_STATE, "current HIP device differs from the engine's device");
-  // group the running slots by (ny, maps storage): one batched launch each
-  std::map<std::pair<long, int>, std::vector<int>> groups;
+  // group the running slots by (ny, maps storage, maps staging): one
+  // batched launch each, running the code path each problem's own launch
+  // would take
+  std::map<std::tuple<long, int, bool>, std::vector<int>> groups;
   for (size_t i = 0; i < e->slots.size(); ++i) {
     const Slot& sl = e->slots[i];
-    if (sl.used && !sl.finishing) groups[{sl.plan->d.ny, sl.plan->d.maps_storage}].push_back((int)i);
+    if (sl.used && !sl.finishing) {
+      const sense_desc& d = sl.plan->d;
+      groups[{d.ny, d.maps_storage, ehe_staged(d.ny, d.maps_storage, d.nx, sl.plan->maps)}].push_back((int)i);
+    }
   }
   int running = 0;
   for (auto& g : groups) running += (int)g.second.size();
@@ -220,11 +226,13 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
       EheInline t{};
       std::copy(he.begin() + off, he.begin() + off + cnt, t.p);
       if (err == hipSuccess)
-        err = launch_ehe_inline(g.first.first, g.first.second, t, cnt, max_tiles, max_groups, e->st);
+        err = launch_ehe_inline(std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first), t, cnt,
+                                max_tiles, max_groups, e->st);
       if (err == hipSuccess && max_groups > 1) err = launch_combine_inline(t, cnt, max_ctiles, e->st);
     } else {
       if (err == hipSuccess)
-        err = launch_ehe_table(g.first.first, g.first.second, e->d_ehe + off, cnt, max_tiles, max_groups, e->st);
+        err = launch_ehe_table(std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first), e->d_ehe + off,
+                               cnt, max_tiles, max_groups, e->st);
       if (err == hipSuccess && max_groups > 1) err = launch_combine_table(e->d_ehe + off, cnt, max_ctiles, e->st);
     }
     off += cnt;

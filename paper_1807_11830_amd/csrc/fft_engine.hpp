@@ -25,6 +25,20 @@
 
 namespace sense {
 
+// Block barrier for the exchanges of a transform that must not wait for the
+// wave's global loads in flight: __syncthreads() also waits for every
+// outstanding global load and store of the wave (its workgroup fence),
+// which would end an asynchronous prefetch at the first exchange.  This one
+// waits for the wave's LDS operations only; the memory clobber keeps the
+// compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <bool LB>
+__device__ __forceinline__ void exchange_barrier() {
+  if constexpr (LB) lds_barrier();
+  else __syncthreads();
+}
+
 template <int... Rs>
 struct Radices {
   static constexpr int count = sizeof...(Rs);
@@ -124,26 +138,27 @@ __device__ __forceinline__ void stockham_stage(c32* v, int t, const Tw& tw, View
 // exchange: the barrier in front of each exchange write keeps it behind the
 // previous exchange's reads (or the previous transform's), and the one after
 // it makes the write visible.
-template <int N, int T, int DIR, int NS, class View, class Tw, int R, int... Rest>
+template <int N, int T, int DIR, int NS, bool LB, class View, class Tw, int R, int... Rest>
 __device__ __forceinline__ void fft_stages(c32* v, int t, const Tw& tw, View b) {
   constexpr bool last = sizeof...(Rest) == 0;
-  if constexpr (!last) __syncthreads();
+  if constexpr (!last) exchange_barrier<LB>();
   stockham_stage<N, T, R, NS, DIR, last>(v, t, tw, b);
   if constexpr (!last) {
-    __syncthreads();
+    exchange_barrier<LB>();
     constexpr int E = N / T;
     sfor<E>([&](auto jc) { v[decltype(jc)::value] = b.at(t + T * decltype(jc)::value); });
-    fft_stages<N, T, DIR, NS * R, View, Tw, Rest...>(v, t, tw, b);
+    fft_stages<N, T, DIR, NS * R, LB, View, Tw, Rest...>(v, t, tw, b);
   }
 }
 
 // Transform of one line held as v[j] = line[t + T j] by its T threads
 // (unnormalised; DIR = -1 forward, +1 inverse); the result returns to the
-// same positions.  b is the line's view of the LDS exchange buffer.
-template <int N, int T, int DIR, class View, class Tw, int... Rs>
+// same positions.  b is the line's view of the LDS exchange buffer.  LB
+// selects LDS-only barriers for the exchanges (see lds_barrier).
+template <int N, int T, int DIR, bool LB = false, class View, class Tw, int... Rs>
 __device__ __forceinline__ void fft_line(c32* v, int t, const Tw& tw, View b, Radices<Rs...>) {
   static_assert(radix_product(Radices<Rs...>{}) == N, "radices must multiply to N");
-  fft_stages<N, T, DIR, 1, View, Tw, Rs...>(v, t, tw, b);
+  fft_stages<N, T, DIR, 1, LB, View, Tw, Rs...>(v, t, tw, b);
 }
 
 // Twiddle source of the fused kernels: registers for two-stage transforms

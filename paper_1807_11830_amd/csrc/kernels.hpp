@@ -180,8 +180,12 @@ hipError_t launch_cg_pupdate(const Geom& g, const c32* r, c32* p, const CgArgs& 
 // combine launch (rows with G = 1 skip it).
 void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, const CgVectors& v, float lambda,
                         int k, const CgArgs& cg, EheParams* out);
-hipError_t launch_ehe_table(long ny, int maps_storage, const EheParams* d_table, int nproblems, int max_tiles,
-                            int max_groups, hipStream_t st);
+// Whether the fused kernel stages this problem's maps tiles through LDS
+// (a property of the problem alone).  Every row of a batched launch must
+// give the same answer; the launch uses that code path for all of them.
+bool ehe_staged(long ny, int maps_storage, long nx, const void* maps);
+hipError_t launch_ehe_table(long ny, int maps_storage, bool staged, const EheParams* d_table, int nproblems,
+                            int max_tiles, int max_groups, hipStream_t st);
 hipError_t launch_combine_table(const EheParams* d_table, int nproblems, int max_tiles, hipStream_t st);
 // The same launches with up to kInlineProblems rows passed by value as the
 // kernel argument (no host-to-device copy of the table).
@@ -189,8 +193,8 @@ constexpr int kInlineProblems = 16;
 struct EheInline {
   EheParams p[kInlineProblems];
 };
-hipError_t launch_ehe_inline(long ny, int maps_storage, const EheInline& table, int nproblems, int max_tiles,
-                             int max_groups, hipStream_t st);
+hipError_t launch_ehe_inline(long ny, int maps_storage, bool staged, const EheInline& table, int nproblems,
+                             int max_tiles, int max_groups, hipStream_t st);
 hipError_t launch_combine_inline(const EheInline& table, int nproblems, int max_tiles, hipStream_t st);
 // Combine pass of one launch (plan path).
 hipError_t launch_combine(const EheParams& P, int batch, bool cg, hipStream_t st);

@@ -28,20 +28,58 @@
 
 namespace sense {
 
+// Maps staged through LDS.  With staging, the next coil's maps tile is
+// copied from HBM straight into LDS (buf_load_lds16: 16 bytes per lane, no
+// register held while the copy is in flight) during the current coil's
+// transforms.  Every wave fills and reads only its own part of the tile, so
+// the copy needs a wait on the wave's own counter and no block barrier, and
+// the transform exchanges use LDS-only barriers that leave it in flight.
+// The tile costs N * TX * (bytes per maps value) of LDS per block.
+// Measured on MI355X (fused CG launch, 12 or 32 coils): with 16-bit maps at
+// 256 points staging halves the launch time for BF16 (597 -> 291 us at 160
+// slices; the register path's 4-byte loads run at half speed there) and
+// matches the register path for FP16; with complex64 maps, and at 160, 192,
+// 320 and 384 points, it is slower or no faster (384 points, 32 coils,
+// complex64: 164 -> 197 us), so only 16-bit maps at 256 points use it.
+constexpr int kLdsBytesPerCU = 160 * 1024;
+template <int N>
+constexpr int ehe_base_lds() {
+  constexpr int NT = EheLen<N>::T * EheLen<N>::TX;
+  return N * EheLen<N>::TX * 8 + N * 8 + N * 4 + 8 * (NT / 64 > 0 ? NT / 64 : 1);
+}
+template <int N, int ST>
+constexpr int ehe_stage_bytes() {
+  return N * EheLen<N>::TX * (ST == ST_C64 ? 8 : 4);
+}
+template <int N, int ST>
+constexpr bool ehe_stage_maps() {
+  if constexpr (ST == ST_C64 || N != 256) {
+    return false;
+  } else {
+    // whole 16-byte chunks per wave and row, and 3 blocks per CU
+    return (EheLen<N>::E * 4) % 16 == 0 && 64 % EheLen<N>::TX == 0 &&
+           3 * (ehe_base_lds<N>() + ehe_stage_bytes<N, ST>() + 512) <= kLdsBytesPerCU;
+  }
+}
 
-template <int N, int ST, bool CG>
+template <int N, int ST, bool CG, bool SM>
 __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, const int b, const int grp) {
   constexpr int T = EheLen<N>::T;
   constexpr int E = EheLen<N>::E;
   constexpr int TX = EheLen<N>::TX;
   constexpr int NT = T * TX;
   using Rad = typename EheLen<N>::R;
+  using SType = typename StorageT<ST>::T;
+  constexpr int SB = (int)sizeof(SType);
 
   // one LDS exchange buffer (each stage boundary waits for its readers)
   __shared__ c32 xbuf[N * TX];
   __shared__ c32 tw[N];
   __shared__ float mu[N];
   __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
+  // the staged maps tile: wave w's part holds its rows j = 0..E-1, one
+  // 64-lane row of values after another
+  __shared__ __attribute__((aligned(16))) unsigned char stage[SM ? ehe_stage_bytes<N, ST>() : 16];
 
   const int tid = threadIdx.x;
   const int cx = tid % TX;
@@ -67,6 +105,46 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   // Columns past nx (ragged last tile) read column nx-1 instead of
   // branching; their results are never stored or reduced.
   const long nvox = (long)N * nx;
+
+  // this block's coil group and its maps
+  const int c0 = (int)((long)grp * P.ncoils / P.ngroups);
+  const int c1 = (int)((long)(grp + 1) * P.ncoils / P.ngroups);
+  const SType* S = static_cast<const SType*>(P.maps) + (long)b * P.maps_bstride;
+  const uint32_t coil_bytes = (uint32_t)(nvox * (long)sizeof(SType));
+
+  // Staged maps: wave wv copies its E rows of coil c into its part of the
+  // tile, 1024 bytes (JI = 1024 / ROWB rows j) per instruction.  A lane's
+  // 16-byte chunk holds 16 / SB values of row j = i JI + lane / (64 / JI),
+  // lanes l0 .. l0 + 16/SB - 1 of that row (never across a row of TX
+  // columns); its offset is the lane's offset for i = 0 plus a uniform
+  // i JI T nx SB.  Rows are whole chunks (nx SB is a multiple of 16 on this
+  // path), so a chunk is either inside the image or wholly past nx, where it
+  // reads nothing (out-of-range offset).
+  [[maybe_unused]] const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  [[maybe_unused]] constexpr int ROWB = 64 * SB;  // bytes of one row j of a wave's part
+  [[maybe_unused]] constexpr int JI = 1024 / ROWB;
+  [[maybe_unused]] unsigned char* const wstage = stage + wv * (E * ROWB);
+  [[maybe_unused]] const uint32_t wstage_lds = lds_address(stage) + (uint32_t)(wv * (E * ROWB));
+  [[maybe_unused]] uint32_t go0 = 0;
+  if constexpr (SM) {
+    const int j = (lane * 16) / ROWB;
+    const int l0 = ((lane * 16) % ROWB) / SB;
+    const uint32_t tt = (uint32_t)(wv * (64 / TX) + l0 / TX);
+    const long col = (long)tile * TX + l0 % TX;
+    go0 = col < nx ? (((tt + (uint32_t)(T * j)) * (uint32_t)nx + (uint32_t)col) * (uint32_t)SB) : kBufOOB;
+  }
+  [[maybe_unused]] auto stage_coil = [&](int c) {
+    const v4i32 rs = make_rsrc(S + (long)c * nvox, coil_bytes);
+    const uint32_t step = (uint32_t)(JI * T) * (uint32_t)nx * (uint32_t)SB;
+    sfor<E / JI>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      buf_load_lds16(rs, wstage_lds + i * 1024, go0, (uint32_t)i * step);
+    });
+  };
+  if constexpr (SM) {
+    if (c0 < c1) stage_coil(c0);  // every copy issued is waited for in the coil loop
+  }
+
   const uint32_t xl = (uint32_t)(valid ? x : nx - 1);
   const uint32_t voff = (uint32_t)t * (uint32_t)nx + xl;  // element offset of row t
   const uint32_t rstep = (uint32_t)T * (uint32_t)nx;      // rows t -> t + T
@@ -149,9 +227,6 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   if constexpr (TwC::regs) twsrc.load(tw, t);
   else twsrc.tw = tw;
 
-  using SType = typename StorageT<ST>::T;
-  const SType* S = static_cast<const SType*>(P.maps) + (long)b * P.maps_bstride;
-  const uint32_t coil_bytes = (uint32_t)(nvox * (long)sizeof(SType));
   LineView<TX> lv{&xbuf[cx]};
 
   auto load_s = [&](c32* s, int c) {
@@ -165,21 +240,31 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     c32 u[E];
 #pragma unroll
     for (int j = 0; j < E; ++j) u[j] = cmul(s[j], p[j]);
-    fft_line<N, T, -1>(u, t, twsrc, lv, Rad{});
+    fft_line<N, T, -1, SM>(u, t, twsrc, lv, Rad{});
 #pragma unroll
     for (int j = 0; j < E; ++j) u[j] = cscale(u[j], mu[t + T * j]);
-    fft_line<N, T, +1>(u, t, twsrc, lv, Rad{});
+    fft_line<N, T, +1, SM>(u, t, twsrc, lv, Rad{});
 #pragma unroll
     for (int j = 0; j < E; ++j) q[j] = cfma_conj(q[j], s[j], u[j]);
   };
 
-  // this block's coil group
-  const int c0 = (int)((long)grp * P.ncoils / P.ngroups);
-  const int c1 = (int)((long)(grp + 1) * P.ncoils / P.ngroups);
-  for (int c = c0; c < c1; ++c) {
-    c32 sc[E];
-    load_s(sc, c);
-    coil(sc);
+  if constexpr (SM) {
+    for (int c = c0; c < c1; ++c) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's copy of coil c
+      c32 sc[E];
+      const SType* ws = reinterpret_cast<const SType*>(wstage) + lane;
+#pragma unroll
+      for (int j = 0; j < E; ++j) sc[j] = load_c<ST>(ws, (long)j * 64);
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // read before the part is refilled
+      if (c + 1 < c1) stage_coil(c + 1);
+      coil(sc);
+    }
+  } else {
+    for (int c = c0; c < c1; ++c) {
+      c32 sc[E];
+      load_s(sc, c);
+      coil(sc);
+    }
   }
 
   if (P.ngroups > 1) {
@@ -238,30 +323,30 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   }
 }
 
-template <int N, int ST, bool CG>
+template <int N, int ST, bool CG, bool SM>
 __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX) ehe2d_kernel(EheParams P) {
   const BlockId id = xcd_block();
-  ehe2d_body<N, ST, CG>(P, (int)id.x, (int)id.y, (int)id.z);
+  ehe2d_body<N, ST, CG, SM>(P, (int)id.x, (int)id.y, (int)id.z);
 }
 
 // Batched CG launch over many independent single-slice problems of the same
 // ny: block row blockIdx.y runs the problem described by table[blockIdx.y]
 // (its own maps, vectors, partials and CG state), so every problem computes
 // exactly what its own launch would.
-template <int N, int ST>
+template <int N, int ST, bool SM>
 __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX)
     ehe2d_table_kernel(const EheParams* __restrict__ table) {
   const EheParams P = table[blockIdx.y];
   if ((long)blockIdx.x >= (long)P.ntiles || (int)blockIdx.z >= P.ngroups) return;
-  ehe2d_body<N, ST, true>(P, blockIdx.x, 0, blockIdx.z);
+  ehe2d_body<N, ST, true, SM>(P, blockIdx.x, 0, blockIdx.z);
 }
 
 // The same with the table passed by value in the kernel arguments.
-template <int N, int ST>
+template <int N, int ST, bool SM>
 __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX) ehe2d_inline_kernel(EheInline table) {
   const EheParams& P = table.p[blockIdx.y];
   if ((long)blockIdx.x >= (long)P.ntiles || (int)blockIdx.z >= P.ngroups) return;
-  ehe2d_body<N, ST, true>(P, blockIdx.x, 0, blockIdx.z);
+  ehe2d_body<N, ST, true, SM>(P, blockIdx.x, 0, blockIdx.z);
 }
 
 int ehe_tile_width(long ny) {
@@ -295,6 +380,57 @@ static void fill_common(const Geom& g, const Tables& tb, EheParams& P) {
   P.qpart_gstride = (long)g.batch * P.nvox;
 }
 
+// Staged maps need 16-byte aligned rows (nx values of the maps storage) and
+// maps base; other problems take the register path.  The choice depends on
+// the problem alone, so a batched launch computes what a single one does.
+bool ehe_staged(long ny, int maps_storage, long nx, const void* maps) {
+  bool can = false;
+  dispatch_length(ny, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    switch (maps_storage) {
+      case ST_C64: can = ehe_stage_maps<N, ST_C64>(); break;
+      case ST_BF16: can = ehe_stage_maps<N, ST_BF16>(); break;
+      case ST_FP16: can = ehe_stage_maps<N, ST_FP16>(); break;
+      default: break;
+    }
+  });
+  const long sb = maps_storage == ST_C64 ? 8 : 4;
+  return can && (nx * sb) % 16 == 0 && reinterpret_cast<uintptr_t>(maps) % 16 == 0;
+}
+
+template <int N, int ST, bool CG>
+static void launch_ehe_kernel(const Geom& g, const EheParams& P, dim3 grid, dim3 block, hipStream_t st) {
+  if constexpr (ehe_stage_maps<N, ST>()) {
+    if (ehe_staged(N, ST, g.nx, P.maps)) {
+      hipLaunchKernelGGL((ehe2d_kernel<N, ST, CG, true>), grid, block, 0, st, P);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((ehe2d_kernel<N, ST, CG, false>), grid, block, 0, st, P);
+}
+
+template <int N, int ST>
+static void launch_table_kernel(bool staged, const EheParams* d_table, dim3 grid, dim3 block, hipStream_t st) {
+  if constexpr (ehe_stage_maps<N, ST>()) {
+    if (staged) {
+      hipLaunchKernelGGL((ehe2d_table_kernel<N, ST, true>), grid, block, 0, st, d_table);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((ehe2d_table_kernel<N, ST, false>), grid, block, 0, st, d_table);
+}
+
+template <int N, int ST>
+static void launch_inline_kernel(bool staged, const EheInline& table, dim3 grid, dim3 block, hipStream_t st) {
+  if constexpr (ehe_stage_maps<N, ST>()) {
+    if (staged) {
+      hipLaunchKernelGGL((ehe2d_inline_kernel<N, ST, true>), grid, block, 0, st, table);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((ehe2d_inline_kernel<N, ST, false>), grid, block, 0, st, table);
+}
+
 template <bool CG>
 static hipError_t launch_ehe_impl(const Geom& g, const EheParams& P, hipStream_t st) {
   hipError_t err = hipErrorInvalidValue;
@@ -305,9 +441,9 @@ static hipError_t launch_ehe_impl(const Geom& g, const EheParams& P, hipStream_t
     dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)g.batch, (unsigned)P.ngroups);
     dim3 block(T * TX);
     switch (g.maps_storage) {
-      case ST_C64: hipLaunchKernelGGL((ehe2d_kernel<N, ST_C64, CG>), grid, block, 0, st, P); break;
-      case ST_BF16: hipLaunchKernelGGL((ehe2d_kernel<N, ST_BF16, CG>), grid, block, 0, st, P); break;
-      case ST_FP16: hipLaunchKernelGGL((ehe2d_kernel<N, ST_FP16, CG>), grid, block, 0, st, P); break;
+      case ST_C64: launch_ehe_kernel<N, ST_C64, CG>(g, P, grid, block, st); break;
+      case ST_BF16: launch_ehe_kernel<N, ST_BF16, CG>(g, P, grid, block, st); break;
+      case ST_FP16: launch_ehe_kernel<N, ST_FP16, CG>(g, P, grid, block, st); break;
       default: return;
     }
     err = hipGetLastError();
@@ -343,17 +479,17 @@ void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, const
   *out = P;
 }
 
-hipError_t launch_ehe_table(long ny, int maps_storage, const EheParams* d_table, int nproblems, int max_tiles,
-                            int max_groups, hipStream_t st) {
+hipError_t launch_ehe_table(long ny, int maps_storage, bool staged, const EheParams* d_table, int nproblems,
+                            int max_tiles, int max_groups, hipStream_t st) {
   hipError_t err = hipErrorInvalidValue;
   dispatch_length(ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     dim3 grid((unsigned)max_tiles, (unsigned)nproblems, (unsigned)max_groups);
     dim3 block(EheLen<N>::T * EheLen<N>::TX);
     switch (maps_storage) {
-      case ST_C64: hipLaunchKernelGGL((ehe2d_table_kernel<N, ST_C64>), grid, block, 0, st, d_table); break;
-      case ST_BF16: hipLaunchKernelGGL((ehe2d_table_kernel<N, ST_BF16>), grid, block, 0, st, d_table); break;
-      case ST_FP16: hipLaunchKernelGGL((ehe2d_table_kernel<N, ST_FP16>), grid, block, 0, st, d_table); break;
+      case ST_C64: launch_table_kernel<N, ST_C64>(staged, d_table, grid, block, st); break;
+      case ST_BF16: launch_table_kernel<N, ST_BF16>(staged, d_table, grid, block, st); break;
+      case ST_FP16: launch_table_kernel<N, ST_FP16>(staged, d_table, grid, block, st); break;
       default: return;
     }
     err = hipGetLastError();
@@ -361,8 +497,8 @@ hipError_t launch_ehe_table(long ny, int maps_storage, const EheParams* d_table,
   return err;
 }
 
-hipError_t launch_ehe_inline(long ny, int maps_storage, const EheInline& table, int nproblems, int max_tiles,
-                             int max_groups, hipStream_t st) {
+hipError_t launch_ehe_inline(long ny, int maps_storage, bool staged, const EheInline& table, int nproblems,
+                             int max_tiles, int max_groups, hipStream_t st) {
   if (nproblems > kInlineProblems) return hipErrorInvalidValue;
   hipError_t err = hipErrorInvalidValue;
   dispatch_length(ny, [&](auto nc) {
@@ -370,9 +506,9 @@ hipError_t launch_ehe_inline(long ny, int maps_storage, const EheInline& table, 
     dim3 grid((unsigned)max_tiles, (unsigned)nproblems, (unsigned)max_groups);
     dim3 block(EheLen<N>::T * EheLen<N>::TX);
     switch (maps_storage) {
-      case ST_C64: hipLaunchKernelGGL((ehe2d_inline_kernel<N, ST_C64>), grid, block, 0, st, table); break;
-      case ST_BF16: hipLaunchKernelGGL((ehe2d_inline_kernel<N, ST_BF16>), grid, block, 0, st, table); break;
-      case ST_FP16: hipLaunchKernelGGL((ehe2d_inline_kernel<N, ST_FP16>), grid, block, 0, st, table); break;
+      case ST_C64: launch_inline_kernel<N, ST_C64>(staged, table, grid, block, st); break;
+      case ST_BF16: launch_inline_kernel<N, ST_BF16>(staged, table, grid, block, st); break;
+      case ST_FP16: launch_inline_kernel<N, ST_FP16>(staged, table, grid, block, st); break;
       default: return;
     }
     err = hipGetLastError();

@@ -181,6 +181,42 @@ def test_eq1_fully_sampled_on_gpu():
     assert rel_l2(got, ref) <= TOL_FP32
 
 
+STAGED_CASES = [  # ny, nx, ncoils, batch, maps storage
+    (256, 36, 7, 2, "bf16"),    # maps staged through LDS; ragged 3rd tile
+    (256, 8, 4, 1, "fp16"),     # staged; one half-empty tile
+    (256, 64, 16, 1, "bf16"),   # staged; 8 coil groups of 2
+    (256, 26, 3, 1, "bf16"),    # rows not 16-byte aligned: register path
+    (384, 100, 9, 2, "c64"),    # register path: 13 tiles of 8 columns, the last with 4
+    (384, 48, 32, 1, "bf16"),   # register path: 16 coil groups of 2
+    (320, 40, 5, 2, "bf16"),
+    (192, 64, 5, 2, "fp16"),
+]
+
+
+@pytest.mark.parametrize("ny,nx,nc,b,storage", STAGED_CASES)
+def test_staged_maps_match_oracle(ny, nx, nc, b, storage):
+    """The fused kernel with 16-bit maps staged through LDS (256-point
+    columns with 16-byte aligned rows) and on its register path, against the
+    oracle on the quantised maps at the fp32 bar, with ragged column tiles
+    and coil groups: the apply, and a 6-iteration CG where nx is a transform
+    length (E^H needs it)."""
+    log(f"staged EHE ny={ny} nx={nx} C={nc} B={b} {storage}")
+    maps, x, mask = rand_case(ny, nx, nc, b, True, seed=ny + 7 * nx + nc)
+    mq = quantise(maps, storage)
+    with sense.Plan(to_dev(maps), mask, batch=b, maps_storage=storage) as plan:
+        log(f"  coil groups {plan.coil_groups()}")
+        q = to_host(plan.EHE(to_dev(x)))
+        err = rel_l2(q, oracle.A(x, mq, mask))
+        log(f"  rel-L2 EHE {err:.3e}")
+        assert err <= TOL_FP32
+        if nx in sense.SUPPORTED_LENGTHS:
+            y = c64(synth.complex_normal((b, nc, ny, nx), ny + nx)) * mask[None, None, :, None]
+            xo, _, _, _ = oracle.cg(y, mq, mask, 6)
+            err = rel_l2(to_host(plan.cg(to_dev(y), 6).x), xo)
+            log(f"  rel-L2 CG {err:.3e}")
+            assert err <= TOL_FP32
+
+
 @pytest.mark.parametrize("storage", ["bf16", "fp16"])
 def test_reduced_precision_maps(storage):
     """16-bit maps: GPU arithmetic vs the oracle on the quantised maps at the
