@@ -199,6 +199,30 @@ def run_serving(args):
                       "runs": runs}), flush=True)
 
 
+VALU_PEAK_TFLOPS = 78.6  # fp32 FMA without packed instructions: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz
+
+
+def precision_roofline(st, n, C, B, K, launch_s):
+    """Both bounds of one fused CG launch over B slices of n x n with C coils
+    in storage st: HBM bytes (maps once in st, x, r, p, q read and written in
+    complex64, averaged over the K launches of a solve) and fp32 flops
+    (C forward/inverse n-point transform pairs at 5 n log2 n each per column,
+    plus 16 flops per element and coil for the coil products and the mask)."""
+    import math
+
+    nvox = n * n
+    sb = 8 if st == "c64" else 4
+    by = B * nvox * (sb * C + (8 * 3 + (K - 1) * 8 * 8) / K)
+    fl = B * nvox * C * (10 * math.log2(n) + 16)
+    t_hbm = by / (HBM_PEAK_GBS * 1e9)
+    t_alu = fl / (VALU_PEAK_TFLOPS * 1e12)
+    bound = "hbm" if t_hbm >= t_alu else "alu"
+    return {"avg_launch_us": launch_s * 1e6, "bytes": round(by), "flops": round(fl),
+            "hbm_time_us": t_hbm * 1e6, "alu_time_us": t_alu * 1e6, "bound": bound,
+            "frac": max(t_hbm, t_alu) / launch_s, "achieved_gbs": by / launch_s / 1e9,
+            "achieved_tflops": fl / launch_s / 1e12}
+
+
 def run_precision(args):
     """384x384, 32 coils, 8 slices, VD R=4, 40 iterations: maps and k-space
     in c64 / bf16 / fp16 storage (fp32 arithmetic, fp64 reductions); solves/s
@@ -233,8 +257,16 @@ def run_precision(args):
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / reps
             xs[st] = plan.cg(ys, K).x.clone()
-            out[st] = {"solve_ms": dt * 1e3, "applies_per_s": B * K / dt}
-        log(f"precision: {st} {dt*1e3:.2f} ms/solve")
+            # per-launch times of the fused CG launch (group launch + combine)
+            plan.set_profiling(True)
+            plan.cg(ys, K, sync=False)
+            torch.cuda.synchronize()
+            n_l, ms_l = plan.profile()
+            plan.set_profiling(False)
+            launch_s = ms_l / 1e3 / max(n_l, 1)
+            out[st] = {"solve_ms": dt * 1e3, "applies_per_s": B * K / dt,
+                       "fused_launch": precision_roofline(st, n, C, B, K, launch_s)}
+        log(f"precision: {st} {dt*1e3:.2f} ms/solve, fused launch {launch_s*1e6:.1f} us")
     for st in ("bf16", "fp16"):
         d = xs[st] - xs["c64"]
         out[st]["rel_l2_vs_gpu_c64_max_over_slices"] = float(
@@ -496,7 +528,7 @@ def run_cgsense(args):
         "roofline": {"bound": "hbm", "kernel": "ehe2d_kernel (fused CG iteration: x, r, p updates + E^H E)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("sense::ehe2d_kernel<256, 0, true>"),
+                     "traffic": measured_traffic("sense::ehe2d_kernel<256, 0, true, false>"),
                      "avg_launch_us": avg_s * 1e6, "launches": n_l,
                      "bytes_per_launch": round(bytes_launch)},
         "ehe_apply": {"avg_launch_us": apply_s * 1e6, "bytes_per_launch": apply_bytes,
