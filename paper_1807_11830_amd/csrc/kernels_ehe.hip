@@ -105,6 +105,11 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   // Columns past nx (ragged last tile) read column nx-1 instead of
   // branching; their results are never stored or reduced.
   const long nvox = (long)N * nx;
+  const uint32_t xl = (uint32_t)(valid ? x : nx - 1);
+  const uint32_t voff = (uint32_t)t * (uint32_t)nx + xl;  // element offset of row t
+  const uint32_t rstep = (uint32_t)T * (uint32_t)nx;      // rows t -> t + T
+  const uint32_t img_bytes = (uint32_t)(nvox * (long)sizeof(c32));
+  const Buf bq = make_buf(P.q + (long)b * nvox, img_bytes);
 
   // this block's coil group and its maps
   const int c0 = (int)((long)grp * P.ncoils / P.ngroups);
@@ -145,11 +150,6 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     if (c0 < c1) stage_coil(c0);  // every copy issued is waited for in the coil loop
   }
 
-  const uint32_t xl = (uint32_t)(valid ? x : nx - 1);
-  const uint32_t voff = (uint32_t)t * (uint32_t)nx + xl;  // element offset of row t
-  const uint32_t rstep = (uint32_t)T * (uint32_t)nx;      // rows t -> t + T
-  const uint32_t img_bytes = (uint32_t)(nvox * (long)sizeof(c32));
-  const Buf bq = make_buf(P.q + (long)b * nvox, img_bytes);
   c32 p[E], q[E];
   [[maybe_unused]] double rho_acc = 0.0;
   if constexpr (!CG) {

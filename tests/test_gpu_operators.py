@@ -212,9 +212,14 @@ def test_staged_maps_match_oracle(ny, nx, nc, b, storage):
         if nx in sense.SUPPORTED_LENGTHS:
             y = c64(synth.complex_normal((b, nc, ny, nx), ny + nx)) * mask[None, None, :, None]
             xo, _, _, _ = oracle.cg(y, mq, mask, 6)
-            err = rel_l2(to_host(plan.cg(to_dev(y), 6).x), xo)
+            yd = to_dev(y)
+            xd = torch.empty((b, ny, nx), dtype=torch.complex64, device=yd.device)
+            x1 = plan.cg(yd, 6, out=xd).x.clone()
+            x2 = plan.cg(yd, 6, out=xd).x  # same arguments: replayed from the captured graph
+            err = rel_l2(to_host(x1), xo)
             log(f"  rel-L2 CG {err:.3e}")
             assert err <= TOL_FP32
+            assert torch.equal(x1, x2)
 
 
 @pytest.mark.parametrize("storage", ["bf16", "fp16"])
