@@ -18,7 +18,8 @@ struct Layout {
   size_t total;
   int eta_tiles, rr_tiles;
   int ngroups;   // coil groups the workspace holds (the fill split)
-  int dgroups;   // the plan's default (ngroups, or 1 for small slices)
+  int dgroups;   // default of the normal operator and CG
+  int agroups;   // default of the E^H column pass and RSS
 };
 
 sense_status fail(sense_status s, const std::string& msg);
@@ -46,7 +47,8 @@ struct sense_plan_s {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used;
   bool busy;  // owned by a serving-engine slot
-  int ngroups;  // coil groups of the 2D normal operator (1 .. L.ngroups)
+  int ngroups;      // coil groups of the 2D normal operator and CG (1 .. L.ngroups)
+  int adj_groups;   // coil groups of the E^H column pass and RSS (1 .. L.ngroups)
   // whole-solve graph, replayed while the solve arguments repeat
   bool graphs;
   hipStream_t cap_stream;
@@ -83,6 +85,8 @@ struct sense_plan_s {
     v.ngroups = ngroups;
     return v;
   }
+  // the [G][B][nvox] partial sums (null when the workspace holds one group)
+  sense::c32* qpart() const { return L.ngroups > 1 ? at<sense::c32>(L.qpart) : nullptr; }
   CgArgs cg_args(double tol, double* hist, int hist_len) const {
     CgArgs a{};
     a.state = at<sense::CgState>(L.state);
