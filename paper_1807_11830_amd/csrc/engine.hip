@@ -11,8 +11,10 @@
 // coil groups, so a problem computes exactly what its own launch would
 // (results are bitwise the same alone or in any mix).  Requests admitted between steps start on the next step; finished
 // slots are reported by poll and freed.  Everything is enqueued on the
-// engine's stream; the host never waits for the device except in poll's
-// event queries and the reuse of a table staging buffer.
+// engine's stream, except that the groups of one step after the first run
+// on up to kLanes side streams forked from and joined back into it (the
+// groups touch disjoint problems); the host never waits for the device
+// except in poll's event queries and the reuse of a table staging buffer.
 #include <algorithm>
 #include <map>
 #include <new>
@@ -61,6 +63,12 @@ struct sense_engine_s {
   // behind a new request grows with the load)
   static constexpr int kAhead = 2;
   hipEvent_t stepped[kAhead] = {};
+  // side streams for the second and later groups of a step (default
+  // priority, like the engine's stream)
+  static constexpr int kLanes = 3;
+  hipStream_t lane[kLanes] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t joined[kLanes] = {};
 };
 
 static void engine_free(sense_engine e) {
@@ -74,6 +82,14 @@ static void engine_free(sense_engine e) {
   }
   for (auto& ev : e->stepped)
     if (ev) (void)hipEventDestroy(ev);
+  for (int i = 0; i < sense_engine_s::kLanes; ++i) {
+    if (e->lane[i]) {
+      (void)hipStreamSynchronize(e->lane[i]);
+      (void)hipStreamDestroy(e->lane[i]);
+    }
+    if (e->joined[i]) (void)hipEventDestroy(e->joined[i]);
+  }
+  if (e->fork) (void)hipEventDestroy(e->fork);
   if (e->d_ehe) (void)hipFree(e->d_ehe);
   if (e->st) (void)hipStreamDestroy(e->st);
   delete e;
@@ -98,6 +114,11 @@ sense_status sense_engine_create(size_t budget_bytes, int32_t max_slots, sense_e
   }
   for (auto& ev : e->stepped)
     if (err == hipSuccess) err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  for (int i = 0; i < sense_engine_s::kLanes && err == hipSuccess; ++i) {
+    err = hipStreamCreateWithFlags(&e->lane[i], hipStreamNonBlocking);
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&e->joined[i], hipEventDisableTiming);
+  }
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&e->fork, hipEventDisableTiming);
   for (auto& s : e->slots)
     if (err == hipSuccess) err = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
   if (err != hipSuccess) {
@@ -211,8 +232,19 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
     e->buf ^= 1;
   }
 
-  int off = 0;
+  // group 0 runs on the engine's stream, group i > 0 on side stream
+  // (i - 1) mod kLanes, forked after the table copy and joined before the
+  // step's event
+  constexpr int L = sense_engine_s::kLanes;
+  const int nlanes = std::min((int)groups.size() - 1, L);
+  if (nlanes > 0 && err == hipSuccess) {
+    err = hipEventRecord(e->fork, e->st);
+    for (int i = 0; i < nlanes && err == hipSuccess; ++i) err = hipStreamWaitEvent(e->lane[i], e->fork, 0);
+  }
+  int off = 0, gi = 0;
   for (auto& g : groups) {
+    hipStream_t gs = gi == 0 ? e->st : e->lane[(gi - 1) % L];
+    ++gi;
     const int cnt = (int)g.second.size();
     int max_tiles = 0, max_groups = 1, max_ctiles = 0;
     for (int j = 0; j < cnt; ++j) {
@@ -227,25 +259,28 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
       std::copy(he.begin() + off, he.begin() + off + cnt, t.p);
       if (err == hipSuccess)
         err = launch_ehe_inline(std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first), t, cnt,
-                                max_tiles, max_groups, e->st);
-      if (err == hipSuccess && max_groups > 1) err = launch_combine_inline(t, cnt, max_ctiles, e->st);
+                                max_tiles, max_groups, gs);
+      if (err == hipSuccess && max_groups > 1) err = launch_combine_inline(t, cnt, max_ctiles, gs);
     } else {
       if (err == hipSuccess)
         err = launch_ehe_table(std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first), e->d_ehe + off,
-                               cnt, max_tiles, max_groups, e->st);
-      if (err == hipSuccess && max_groups > 1) err = launch_combine_table(e->d_ehe + off, cnt, max_ctiles, e->st);
+                               cnt, max_tiles, max_groups, gs);
+      if (err == hipSuccess && max_groups > 1) err = launch_combine_table(e->d_ehe + off, cnt, max_ctiles, gs);
     }
     off += cnt;
-  }
-  for (auto& g : groups)
     for (int i : g.second) {
       Slot& sl = e->slots[(size_t)i];
       if (++sl.k == sl.K && err == hipSuccess) {
-        err = enqueue_solve_end(sl.plan, sl.x, sl.K, sl.plan->cg_args(sl.tol, nullptr, 0), nullptr, e->st);
-        if (err == hipSuccess) err = hipEventRecord(sl.done, e->st);
+        err = enqueue_solve_end(sl.plan, sl.x, sl.K, sl.plan->cg_args(sl.tol, nullptr, 0), nullptr, gs);
+        if (err == hipSuccess) err = hipEventRecord(sl.done, gs);
         sl.finishing = true;
       }
     }
+  }
+  for (int i = 0; i < nlanes && err == hipSuccess; ++i) {
+    err = hipEventRecord(e->joined[i], e->lane[i]);
+    if (err == hipSuccess) err = hipStreamWaitEvent(e->st, e->joined[i], 0);
+  }
   if (err == hipSuccess) err = hipEventRecord(e->stepped[e->steps % sense_engine_s::kAhead], e->st);
   ++e->steps;
   return err == hipSuccess ? SENSE_OK : device_fail(err, "sense_engine_step");
