@@ -250,13 +250,17 @@ SENSE_API sense_status sense_plan_profile(sense_plan plan, int64_t* n_launches, 
  * buffers) within the remaining budget; otherwise it returns
  * SENSE_ERR_STATE and the caller retries after poll has freed slots.  A step
  * advances every running slot by one CG iteration with one batched launch of
- * the fused normal operator and one batched update per distinct (ny, maps
- * storage) group; each problem uses its own CG state and reduction order, so
- * its result is bitwise the same as sense_cg_solve alone.  Requests admitted
- * between steps join at the next step.  poll returns the slots whose solves
- * are complete (d_x written; sense_plan_cg_info gives the info) and frees
- * them.  The engine owns one stream; a plan in a slot must not be used or
- * destroyed until its slot is polled.  All calls come from one host thread.
+ * the fused iteration (and, where a problem splits its coils, one combine
+ * launch) per distinct (ny, maps storage, maps staging) group; each problem
+ * uses its own CG state, coil groups and reduction order, so its result is
+ * bitwise the same as sense_cg_solve alone.  Requests admitted between steps
+ * join at the next step.  poll returns the slots whose solves are complete
+ * (d_x written; sense_plan_cg_info gives the info) and frees them.  The
+ * engine owns its streams: admissions and steps are ordered on one of them,
+ * and the groups of a step after the first run on side streams forked from
+ * and joined back into it (sense_engine_sync waits for all).  A plan in a
+ * slot must not be used or destroyed until its slot is polled.  All calls
+ * come from one host thread.
  */
 typedef struct sense_engine_s* sense_engine;
 
