@@ -212,10 +212,8 @@ SENSE_API sense_status sense_plan_set_graphs(sense_plan plan, int32_t enable);
  * The E^H column pass and RSS split the same way (their own combine).
  * The plan sizes its workspace at creation for the fill split Gmax (1 when
  * tiles x batch >= 512, else ceil(512 / (tiles x batch)) capped at coils / 2
- * and 16).  It starts E^H E and CG at G = min(Gmax, max(1, coils / 4)) (at
- * least four coils per group, as they combine every iteration) and E^H and
- * RSS at Gmax, all at 1 when a slice has fewer than 8192 voxels (there the
- * combine pass costs more than the split saves).
+ * and 16) and starts at G = Gmax, or at G = 1 when a slice has fewer than
+ * 8192 voxels (there the combine pass costs more than the split saves).
  *   sense_plan_set_coil_groups: groups = 0 restores the plan's defaults;
  *     1 <= groups <= Gmax sets G for all of them (1 = no split).
  *     Larger values return SENSE_ERR_UNSUPPORTED.  Results depend on G only

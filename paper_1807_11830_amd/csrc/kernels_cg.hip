@@ -11,6 +11,7 @@
 // vectors are fp32 complex.  Every block of a batch element reduces the same
 // partials in the same order, so all blocks take the same decisions and the
 // results do not depend on scheduling.
+#include "bufio.hpp"
 #include "cg_scalar.hpp"
 #include "kernels.hpp"
 #include "reduce.hpp"
@@ -239,18 +240,32 @@ __device__ __forceinline__ void combine_body(const EheParams& P, const int b, co
   if (base >= lim) return;
   const c32* pk = cg ? P.p_out : P.p_in;
   const float lam = P.lambda;
+  const int G = P.ngroups;
+  // all G partials of an access are loaded before the first is added (a
+  // load-add loop would wait for each load in turn); groups past G use an
+  // out-of-range offset, which reads nothing
+  const Buf bg = make_buf(P.qpart, (uint32_t)((long)G * P.qpart_gstride * (long)sizeof(c32)));
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
+#pragma unroll 1
   for (int s = 0; s < CG_STEPS; ++s) {
     const long i = base + ((long)s * CG_NT + threadIdx.x) * CG_VEC;
     if (i < lim) {
-      c32x2 qs = *reinterpret_cast<const c32x2*>(P.qpart + i);
-      for (int gr = 1; gr < P.ngroups; ++gr) {
-        const c32x2 t = *reinterpret_cast<const c32x2*>(P.qpart + (long)gr * P.qpart_gstride + i);
-        qs.a.re += t.a.re;
-        qs.a.im += t.a.im;
-        qs.b.re += t.b.re;
-        qs.b.im += t.b.im;
+      c32x2 t[kMaxCoilGroups];
+#pragma unroll
+      for (int gr = 0; gr < kMaxCoilGroups; ++gr) {
+        const uint32_t off = gr < G ? (uint32_t)(((long)gr * P.qpart_gstride + i) * (long)sizeof(c32)) : kBufOOB;
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(bg.r, (int)off, 0, 0);
+        t[gr] = __builtin_bit_cast(c32x2, w);
+      }
+      c32x2 qs = t[0];
+#pragma unroll
+      for (int gr = 1; gr < kMaxCoilGroups; ++gr) {
+        if (gr < G) {
+          qs.a.re += t[gr].a.re;
+          qs.a.im += t[gr].a.im;
+          qs.b.re += t[gr].b.re;
+          qs.b.im += t[gr].b.im;
+        }
       }
       c32x2 pv = {{0.f, 0.f}, {0.f, 0.f}};
       if (pk) pv = *reinterpret_cast<const c32x2*>(pk + i);

@@ -59,18 +59,17 @@ static Layout make_layout(const sense_desc& d) {
   }
   L.rr_tiles = cg_tiles((long)nvox);
   L.ngroups = d.ndim == 2 ? auto_coil_groups(d.nx, d.ny, d.ncoils, d.batch) : 1;
-  // Default splits.  None below kMinSplitVoxels per slice, where the
-  // combine launch costs more than the split saves.  The normal operator
-  // and CG, which combine once per iteration, keep at least 4 coils per
-  // group (the partial sums the combine writes and re-reads then stay within
-  // half of the maps traffic); the single E^H column pass and RSS use the
-  // fill split.  Measured on MI355X, 20 CG iterations: 64^2 x 4 coils 229 us
-  // unsplit, 285 us at G = 2; 96^2 x 8 coils 504 us unsplit, 402 us at
-  // G = 4; 320^2 x 32 coils 1.151 ms at G = 16, 1.087 ms at G = 8; 192^2 x
-  // 16 coils x 4 slices 0.763 ms at G = 8, 0.704 ms at G = 4; the serving
-  // workload's engine capacity rose from 4,079 to 4,744 solves/s.
+  // Default splits: the fill split, and none below kMinSplitVoxels per
+  // slice, where the combine launch costs more than the split saves
+  // (measured on MI355X, 20 CG iterations: 64^2 x 4 coils 229 us unsplit,
+  // 285 us at G = 2; 96^2 x 8 coils 504 us unsplit, 402 us at G = 4).  With
+  // the combine's group partials loaded together, whole solves take the
+  // fill split too (320^2 x 32 coils: 0.893 ms at G = 16, 0.974 ms at
+  // G = 8; 256^2 x 16 coils: 0.593 ms at G = 8, 0.705 ms at G = 4).  The
+  // normal operator with CG, and the E^H column pass with RSS, keep
+  // separate settings (both the fill split by default).
   const bool small = (long)d.nx * d.ny < kMinSplitVoxels;
-  L.dgroups = small ? 1 : std::min(L.ngroups, std::max(1, (int)d.ncoils / 4));
+  L.dgroups = small ? 1 : L.ngroups;
   L.agroups = small ? 1 : L.ngroups;
   size_t off = 0;
   auto take = [&](size_t bytes) {

@@ -38,10 +38,10 @@ def test_ehe_matches_oracle(ny, nx, nc, b, per):
 
 
 def test_ehe_coil_groups():
-    """5 column tiles x 2 slices fill few blocks, so the plan's workspace
-    holds 3 coil groups (2, 2 and 3 coils) for E^H E, E^H and RSS (its
-    default keeps at least 4 coils per group: one group here); every split
-    gives the same operators to the fp32 bar."""
+    """5 column tiles x 2 slices fill few blocks, so the plan splits the 7
+    coils into 3 groups (2, 2 and 3 coils) for E^H E, E^H and RSS; a forced
+    smaller, uneven split and no split give the same operators to the fp32
+    bar."""
     maps, x, mask = rand_case(128, 80, 7, 2, True, seed=9)
     y = c64(synth.complex_normal((2, 7, 128, 80), 10))
     ref = oracle.A(x, maps, mask, lam=0.2)
@@ -49,7 +49,7 @@ def test_ehe_coil_groups():
     ref_r = oracle.rss(y * mask[None, None, :, None])
     with sense.Plan(to_dev(maps), mask, batch=2) as plan:
         g, gmax = plan.coil_groups()
-        assert (g, gmax) == (1, 3)
+        assert (g, gmax) == (3, 3)
         for G in (1, 2, 3):
             plan.set_coil_groups(G)
             q = to_host(plan.EHE(to_dev(x), lam=0.2))
@@ -61,7 +61,7 @@ def test_ehe_coil_groups():
         with pytest.raises(sense.SenseError, match="coil groups"):
             plan.set_coil_groups(gmax + 1)
         plan.set_coil_groups(0)
-        assert plan.coil_groups() == (1, gmax)
+        assert plan.coil_groups() == (gmax, gmax)
 
 
 def test_ehe_lambda():
