@@ -260,12 +260,12 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
       if (err == hipSuccess)
         err = launch_ehe_inline(std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first), t, cnt,
                                 max_tiles, max_groups, gs);
-      if (err == hipSuccess && max_groups > 1) err = launch_combine_inline(t, cnt, max_ctiles, gs);
+      if (err == hipSuccess && max_groups > 1) err = launch_combine_inline(t, cnt, max_ctiles, max_groups, gs);
     } else {
       if (err == hipSuccess)
         err = launch_ehe_table(std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first), e->d_ehe + off,
                                cnt, max_tiles, max_groups, gs);
-      if (err == hipSuccess && max_groups > 1) err = launch_combine_table(e->d_ehe + off, cnt, max_ctiles, gs);
+      if (err == hipSuccess && max_groups > 1) err = launch_combine_table(e->d_ehe + off, cnt, max_ctiles, max_groups, gs);
     }
     off += cnt;
     for (int i : g.second) {

@@ -186,7 +186,8 @@ void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, const
 bool ehe_staged(long ny, int maps_storage, long nx, const void* maps);
 hipError_t launch_ehe_table(long ny, int maps_storage, bool staged, const EheParams* d_table, int nproblems,
                             int max_tiles, int max_groups, hipStream_t st);
-hipError_t launch_combine_table(const EheParams* d_table, int nproblems, int max_tiles, hipStream_t st);
+hipError_t launch_combine_table(const EheParams* d_table, int nproblems, int max_tiles, int max_groups,
+                                hipStream_t st);
 // The same launches with up to kInlineProblems rows passed by value as the
 // kernel argument (no host-to-device copy of the table).
 constexpr int kInlineProblems = 16;
@@ -195,7 +196,8 @@ struct EheInline {
 };
 hipError_t launch_ehe_inline(long ny, int maps_storage, bool staged, const EheInline& table, int nproblems,
                              int max_tiles, int max_groups, hipStream_t st);
-hipError_t launch_combine_inline(const EheInline& table, int nproblems, int max_tiles, hipStream_t st);
+hipError_t launch_combine_inline(const EheInline& table, int nproblems, int max_tiles, int max_groups,
+                                 hipStream_t st);
 // Combine pass of one launch (plan path).
 hipError_t launch_combine(const EheParams& P, int batch, bool cg, hipStream_t st);
 

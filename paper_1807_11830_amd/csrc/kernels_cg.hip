@@ -228,10 +228,18 @@ hipError_t launch_cg_fused_final(const Geom& g, const CgVectors& v, int K, const
 }
 
 // Coil-group combine of one problem row: q = sum_g qpart[g] + lambda p, the
-// groups added in index order (no lambda p when p is null: the E^H combine).  CG mode (P.state set) also emits the fp64
-// partials Re<p,q>, Re<r,q>, <q,q>, <r,r> of launch k into part4[k & 1]
-// (one entry per block of this kernel) and skips a problem that has stopped.
+// groups added in index order (no lambda p when p is null: the E^H combine).
+// CG mode (P.state set) also emits the fp64 partials Re<p,q>, Re<r,q>,
+// <q,q>, <r,r> of launch k into part4[k & 1] (one entry per block of this
+// kernel) and skips a problem that has stopped.  GB >= G slots: the loads of
+// SU accesses (every group partial, p and r) are all issued before the first
+// add, so a thread waits for memory once per SU accesses rather than once
+// per partial; groups past G and accesses past the end use an out-of-range
+// buffer offset, which reads nothing.
+template <int GB>
 __device__ __forceinline__ void combine_body(const EheParams& P, const int b, const int tile, const bool cg) {
+  constexpr int SU = GB <= 4 ? 4 : (GB <= 8 ? 2 : 1);
+  static_assert(CG_STEPS % SU == 0, "access batches must divide the steps");
   __shared__ double red[CG_NT / 64];
   if (cg && P.state[b].status != CG_RUNNING) return;
   const long nvox = P.nvox;
@@ -241,48 +249,58 @@ __device__ __forceinline__ void combine_body(const EheParams& P, const int b, co
   const c32* pk = cg ? P.p_out : P.p_in;
   const float lam = P.lambda;
   const int G = P.ngroups;
-  // all G partials of an access are loaded before the first is added (a
-  // load-add loop would wait for each load in turn); groups past G use an
-  // out-of-range offset, which reads nothing
+  const uint32_t vbytes = (uint32_t)(lim * (long)sizeof(c32));
   const Buf bg = make_buf(P.qpart, (uint32_t)((long)G * P.qpart_gstride * (long)sizeof(c32)));
+  const Buf bp = make_buf(pk, pk ? vbytes : 0u);
+  const Buf br = make_buf(P.r_out, cg ? vbytes : 0u);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-  for (int s = 0; s < CG_STEPS; ++s) {
-    const long i = base + ((long)s * CG_NT + threadIdx.x) * CG_VEC;
-    if (i < lim) {
-      c32x2 t[kMaxCoilGroups];
 #pragma unroll
-      for (int gr = 0; gr < kMaxCoilGroups; ++gr) {
-        const uint32_t off = gr < G ? (uint32_t)(((long)gr * P.qpart_gstride + i) * (long)sizeof(c32)) : kBufOOB;
-        const auto w = __builtin_amdgcn_raw_buffer_load_b128(bg.r, (int)off, 0, 0);
-        t[gr] = __builtin_bit_cast(c32x2, w);
+  for (int s0 = 0; s0 < CG_STEPS; s0 += SU) {
+    c32x2 t[SU][GB], pv[SU], rv[SU];
+    long idx[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+      const long i = base + ((long)(s0 + u) * CG_NT + threadIdx.x) * CG_VEC;
+      idx[u] = i;
+      const bool in = i < lim;
+#pragma unroll
+      for (int gr = 0; gr < GB; ++gr) {
+        const uint32_t off =
+            in && gr < G ? (uint32_t)(((long)gr * P.qpart_gstride + i) * (long)sizeof(c32)) : kBufOOB;
+        t[u][gr] = __builtin_bit_cast(c32x2, __builtin_amdgcn_raw_buffer_load_b128(bg.r, (int)off, 0, 0));
       }
-      c32x2 qs = t[0];
+      const uint32_t vo = in ? (uint32_t)(i * (long)sizeof(c32)) : kBufOOB;
+      pv[u] = __builtin_bit_cast(c32x2, __builtin_amdgcn_raw_buffer_load_b128(bp.r, (int)vo, 0, 0));
+      if (cg) rv[u] = __builtin_bit_cast(c32x2, __builtin_amdgcn_raw_buffer_load_b128(br.r, (int)vo, 0, 0));
+    }
 #pragma unroll
-      for (int gr = 1; gr < kMaxCoilGroups; ++gr) {
+    for (int u = 0; u < SU; ++u) {
+      if (idx[u] >= lim) continue;
+      c32x2 qs = t[u][0];
+#pragma unroll
+      for (int gr = 1; gr < GB; ++gr) {
         if (gr < G) {
-          qs.a.re += t[gr].a.re;
-          qs.a.im += t[gr].a.im;
-          qs.b.re += t[gr].b.re;
-          qs.b.im += t[gr].b.im;
+          qs.a.re += t[u][gr].a.re;
+          qs.a.im += t[u][gr].a.im;
+          qs.b.re += t[u][gr].b.re;
+          qs.b.im += t[u][gr].b.im;
         }
       }
-      c32x2 pv = {{0.f, 0.f}, {0.f, 0.f}};
-      if (pk) pv = *reinterpret_cast<const c32x2*>(pk + i);
+      const c32x2 p = pv[u];
       c32x2 qv;
-      qv.a = {qs.a.re + lam * pv.a.re, qs.a.im + lam * pv.a.im};
-      qv.b = {qs.b.re + lam * pv.b.re, qs.b.im + lam * pv.b.im};
-      *reinterpret_cast<c32x2*>(P.q + i) = qv;
+      qv.a = {qs.a.re + lam * p.a.re, qs.a.im + lam * p.a.im};
+      qv.b = {qs.b.re + lam * p.b.re, qs.b.im + lam * p.b.im};
+      *reinterpret_cast<c32x2*>(P.q + idx[u]) = qv;
       if (cg) {
-        const c32x2 rv = *reinterpret_cast<const c32x2*>(P.r_out + i);
-        acc[0] += (double)pv.a.re * qv.a.re + (double)pv.a.im * qv.a.im + (double)pv.b.re * qv.b.re +
-                  (double)pv.b.im * qv.b.im;
-        acc[1] += (double)rv.a.re * qv.a.re + (double)rv.a.im * qv.a.im + (double)rv.b.re * qv.b.re +
-                  (double)rv.b.im * qv.b.im;
+        const c32x2 r = rv[u];
+        acc[0] += (double)p.a.re * qv.a.re + (double)p.a.im * qv.a.im + (double)p.b.re * qv.b.re +
+                  (double)p.b.im * qv.b.im;
+        acc[1] += (double)r.a.re * qv.a.re + (double)r.a.im * qv.a.im + (double)r.b.re * qv.b.re +
+                  (double)r.b.im * qv.b.im;
         acc[2] += (double)qv.a.re * qv.a.re + (double)qv.a.im * qv.a.im + (double)qv.b.re * qv.b.re +
                   (double)qv.b.im * qv.b.im;
-        acc[3] += (double)rv.a.re * rv.a.re + (double)rv.a.im * rv.a.im + (double)rv.b.re * rv.b.re +
-                  (double)rv.b.im * rv.b.im;
+        acc[3] += (double)r.a.re * r.a.re + (double)r.a.im * r.a.im + (double)r.b.re * r.b.re +
+                  (double)r.b.im * r.b.im;
       }
     }
   }
@@ -296,40 +314,62 @@ __device__ __forceinline__ void combine_body(const EheParams& P, const int b, co
   }
 }
 
-template <bool CG>
+template <bool CG, int GB>
 __global__ void __launch_bounds__(CG_NT) combine_kernel(EheParams P) {
-  combine_body(P, blockIdx.y, blockIdx.x, CG);
+  combine_body<GB>(P, blockIdx.y, blockIdx.x, CG);
 }
 
+template <int GB>
 __global__ void __launch_bounds__(CG_NT) combine_table_kernel(const EheParams* __restrict__ table) {
   const EheParams& P = table[blockIdx.y];
   if (P.ngroups < 2) return;
-  combine_body(P, 0, blockIdx.x, true);
+  combine_body<GB>(P, 0, blockIdx.x, true);
 }
 
+template <int GB>
 __global__ void __launch_bounds__(CG_NT) combine_inline_kernel(EheInline table) {
   const EheParams& P = table.p[blockIdx.y];
   if (P.ngroups < 2) return;
-  combine_body(P, 0, blockIdx.x, true);
+  combine_body<GB>(P, 0, blockIdx.x, true);
 }
 
-hipError_t launch_combine_inline(const EheInline& table, int nproblems, int max_tiles, hipStream_t st) {
-  if (nproblems > kInlineProblems) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(combine_inline_kernel, dim3((unsigned)max_tiles, (unsigned)nproblems), dim3(CG_NT), 0, st,
-                     table);
+// Calls f(std::integral_constant<int, GB>) with the slot count for G groups.
+template <class F>
+static void dispatch_slots(int groups, F&& f) {
+  if (groups <= 2) f(std::integral_constant<int, 2>{});
+  else if (groups <= 4) f(std::integral_constant<int, 4>{});
+  else if (groups <= 8) f(std::integral_constant<int, 8>{});
+  else f(std::integral_constant<int, kMaxCoilGroups>{});
+}
+
+hipError_t launch_combine_inline(const EheInline& table, int nproblems, int max_tiles, int max_groups,
+                                 hipStream_t st) {
+  if (nproblems > kInlineProblems || max_groups > kMaxCoilGroups) return hipErrorInvalidValue;
+  dispatch_slots(max_groups, [&](auto gb) {
+    hipLaunchKernelGGL((combine_inline_kernel<decltype(gb)::value>), dim3((unsigned)max_tiles, (unsigned)nproblems),
+                       dim3(CG_NT), 0, st, table);
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_combine(const EheParams& P, int batch, bool cg, hipStream_t st) {
+  if (P.ngroups > kMaxCoilGroups) return hipErrorInvalidValue;
   dim3 grid((unsigned)cg_tiles(P.nvox), (unsigned)batch);
-  if (cg) hipLaunchKernelGGL(combine_kernel<true>, grid, dim3(CG_NT), 0, st, P);
-  else hipLaunchKernelGGL(combine_kernel<false>, grid, dim3(CG_NT), 0, st, P);
+  dispatch_slots(P.ngroups, [&](auto gb) {
+    constexpr int GB = decltype(gb)::value;
+    if (cg) hipLaunchKernelGGL((combine_kernel<true, GB>), grid, dim3(CG_NT), 0, st, P);
+    else hipLaunchKernelGGL((combine_kernel<false, GB>), grid, dim3(CG_NT), 0, st, P);
+  });
   return hipGetLastError();
 }
 
-hipError_t launch_combine_table(const EheParams* d_table, int nproblems, int max_tiles, hipStream_t st) {
-  hipLaunchKernelGGL(combine_table_kernel, dim3((unsigned)max_tiles, (unsigned)nproblems), dim3(CG_NT), 0, st,
-                     d_table);
+hipError_t launch_combine_table(const EheParams* d_table, int nproblems, int max_tiles, int max_groups,
+                                hipStream_t st) {
+  if (max_groups > kMaxCoilGroups) return hipErrorInvalidValue;
+  dispatch_slots(max_groups, [&](auto gb) {
+    hipLaunchKernelGGL((combine_table_kernel<decltype(gb)::value>), dim3((unsigned)max_tiles, (unsigned)nproblems),
+                       dim3(CG_NT), 0, st, d_table);
+  });
   return hipGetLastError();
 }
 
