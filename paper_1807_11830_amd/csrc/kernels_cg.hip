@@ -238,7 +238,7 @@ hipError_t launch_cg_fused_final(const Geom& g, const CgVectors& v, int K, const
 // buffer offset, which reads nothing.
 template <int GB>
 __device__ __forceinline__ void combine_body(const EheParams& P, const int b, const int tile, const bool cg) {
-  constexpr int SU = GB <= 4 ? 4 : (GB <= 8 ? 2 : 1);
+  constexpr int SU = GB <= 8 ? 4 : 2;
   static_assert(CG_STEPS % SU == 0, "access batches must divide the steps");
   __shared__ double red[CG_NT / 64];
   if (cg && P.state[b].status != CG_RUNNING) return;
