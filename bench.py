@@ -66,15 +66,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=160)
     ap.add_argument("--iters", type=int, default=30)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--maps-storage", default="c64", choices=["c64", "bf16", "fp16"])
     ap.add_argument("--workload", default="cgsense", choices=["cgsense", "serving", "precision", "autograd3d", "paper", "small"],
                     help="cgsense (default, the metric's workload); the others print their own line")
     ap.add_argument("--requests", type=int, default=512)
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also time a 1 GiB device-to-device copy (reference for HBM counters)")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the context figures (copy peak, torch.fft E^H E, serving summary)")
     return ap.parse_args()
 
 
@@ -99,29 +99,163 @@ def make_inputs(w, B, dev):
     return maps, imgs, mask, maps_u[0]
 
 
+def host_info():
+    """What the host offers: logical CPUs, the CPUs this process may use,
+    OMP_NUM_THREADS and the CPU model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "affinity_cpus": affinity,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"), "cpu_model": model}
+
+
 def cpu_baseline(w, maps0, mask, y0, target_s):
-    """FP64 oracle CG on one slice of the workload, iterations bounded so the
-    sample takes about target_s seconds.  Returns applies/s and the sample."""
+    """The FP64 oracle's CG-SENSE on the workload's slices, on the host.
+
+    Every host thread solves its own slice (whole solves: E^H y, then K
+    iterations of the composed E^H(E p), fp64 throughout), one OpenMP thread
+    each, so all cores work; K is chosen so one round takes about target_s/4.
+    The rate counts K applies per solve, like the GPU value.  Reported: the
+    median over 3 rounds, and one slice alone on one thread."""
+    import concurrent.futures as cf
+    import statistics
+
     import oracle
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    hi = host_info()
+    threads = int(hi["omp_num_threads"] or hi["affinity_cpus"])
+    threads = max(1, min(threads, hi["affinity_cpus"]))
     maps0 = maps0.astype(np.complex128)
     y0 = y0.astype(np.complex128)[None]
-    oracle.A(oracle.EH(y0, maps0, mask), maps0, mask)  # warm-up (library load, threads)
-    # whole solves of the workload's iteration count, repeated until ~target_s
-    k = w.iters
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
+
+    def solve(k):
+        oracle.set_threads(1)
         oracle.cg(y0, maps0, mask, k)
-        reps += 1
-        dt = time.perf_counter() - t0
-        if dt >= target_s:
-            break
-    return dict(value=reps * k / dt, unit="applies/s", cores=min(threads, w.ncoils), kind="oracle",
-                sample=f"1 slice {w.n}x{w.n}, {w.ncoils} coils, {reps} x (E^H y + {k} CG iterations), "
-                       f"E^H E composed as E^H(E p) in fp64, {min(threads, w.ncoils)} OpenMP threads "
-                       f"over coils, {dt:.1f} s")
+
+    # single thread: one slice alone, two iterations to size the rounds
+    solve(1)  # library load
+    t0 = time.perf_counter()
+    solve(2)
+    t1 = time.perf_counter() - t0
+    per_apply = t1 / 2.5  # E^H y costs about half an apply
+    k = max(1, int(round((target_s / 4) / per_apply - 0.5)))
+    t0 = time.perf_counter()
+    solve(k)
+    t_single = time.perf_counter() - t0
+    rounds = []
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        for _ in range(3):
+            t0 = time.perf_counter()
+            list(ex.map(solve, [k] * threads))
+            rounds.append(time.perf_counter() - t0)
+    med = statistics.median(rounds)
+    return dict(value=threads * k / med, unit="applies/s", cores=threads, kind="oracle",
+                single_thread_applies_per_s=k / t_single, host=hi,
+                sample=f"{threads} concurrent whole solves of one {w.n}x{w.n} slice with {w.ncoils} coils "
+                       f"(E^H y + {k} CG iterations, E^H E composed as E^H(E p), fp64), one OpenMP thread "
+                       f"each; median of 3 rounds ({', '.join(f'{r:.1f}' for r in rounds)} s); "
+                       f"single thread {k} iterations in {t_single:.1f} s")
+
+
+def copy_peak(dev):
+    """Device-to-device copy of 1 GiB on the same GPU (read + write rate)."""
+    import torch
+
+    src = torch.ones(1 << 27, dtype=torch.complex64, device=dev)  # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    cms = ev0.elapsed_time(ev1) / 5
+    del src, dst
+    return {"ms": cms, "gbs_read_plus_write": 2 * (1 << 30) / cms / 1e6}
+
+
+def library_fft_ehe(maps, imgs, mask, reps=5):
+    """E^H E of the same batch written with torch.fft (rocFFT) for reference:
+    composed (centred 2D transforms of every coil image, mask, inverse,
+    conjugate coil sum) and in the readout-decoupled form (1D transforms
+    along y only).  Times in ms per apply of the whole batch."""
+    import torch
+
+    dev = imgs.device
+    m = torch.from_numpy(mask.astype(np.float32)).to(dev)
+    n = imgs.shape[-2]
+    mu = torch.roll(m, -(n // 2)) / n  # uncentred mask / ny
+
+    def composed():
+        u = maps * imgs[:, None]
+        k = torch.fft.fftshift(torch.fft.fft2(torch.fft.ifftshift(u, dim=(-2, -1)), norm="ortho"), dim=(-2, -1))
+        k = k * m[:, None]
+        v = torch.fft.fftshift(torch.fft.ifft2(torch.fft.ifftshift(k, dim=(-2, -1)), norm="ortho"), dim=(-2, -1))
+        return (maps.conj() * v).sum(1)
+
+    def hybrid():
+        u = torch.fft.fft(maps * imgs[:, None], dim=-2) * mu[:, None]
+        return (maps.conj() * torch.fft.ifft(u, dim=-2, norm="forward")).sum(1)
+
+    out = {}
+    for name, f in (("composed", composed), ("readout_decoupled", hybrid)):
+        f()
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            f()
+        ev1.record()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = ev0.elapsed_time(ev1) / reps
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving_summary(n_requests=512, factor=0.9):
+    """The serving workload at one arrival rate: 512 seeded requests (own
+    maps, image and noise each), Poisson arrivals at factor x the measured
+    one-at-a-time rate; p50/p99 latency and solves/s of the engine (HBM
+    budget) and of one solve at a time."""
+    from paper_1807_11830_amd.serving import EngineExecutor, InputBank, Scheduler, SerialExecutor, make_requests
+
+    bank = InputBank()
+    t0 = time.perf_counter()
+    reqs0 = make_requests(n_requests, rate=1.0)
+    bank.prepare(reqs0)
+    log(f"serving: {n_requests} requests' inputs ({bank.nbytes() / 2**30:.2f} GiB) in "
+        f"{time.perf_counter() - t0:.1f} s")
+    ser = SerialExecutor(bank)
+    Scheduler(ser).run(make_requests(48, rate=1e9))  # warm plans and graphs
+    mu = Scheduler(ser).run(make_requests(96, rate=1e9)).throughput
+    reqs = make_requests(n_requests, rate=factor * mu)
+    ex = EngineExecutor(bank, 200 << 30, max_slots=128)
+    Scheduler(ex).run(make_requests(32, rate=1e9))
+    se = Scheduler(ex).run(reqs)
+    ex.close()
+    reqs = make_requests(n_requests, rate=factor * mu)
+    ss = Scheduler(ser).run(reqs)
+    ser.close()
+    bank.close()
+    res = {"workload": f"serving_{n_requests}req_n128-320_c8-32_r2-4_k25", "arrival_factor": factor,
+           "one_at_a_time_rate": mu, "inputs": "per request (own seeded maps, image, noise)",
+           "engine": {"p50_ms": se.p50 * 1e3, "p99_ms": se.p99 * 1e3, "solves_per_s": se.throughput,
+                      "max_inflight": se.max_inflight, "budget": "HBM (200 GiB)"},
+           "one_at_a_time": {"p50_ms": ss.p50 * 1e3, "p99_ms": ss.p99 * 1e3, "solves_per_s": ss.throughput}}
+    log(f"serving: x{factor} engine p50 {se.p50 * 1e3:.2f} p99 {se.p99 * 1e3:.2f} ms {se.throughput:.0f}/s; "
+        f"one at a time p50 {ss.p50 * 1e3:.2f} p99 {ss.p99 * 1e3:.2f} ms {ss.throughput:.0f}/s")
+    return res
 
 
 def main():
@@ -150,7 +284,7 @@ def run_serving(args):
     bank.prepare(make_requests(args.requests, rate=1.0))
     # warm up plans/graphs, then measure the one-at-a-time rate
     ser = SerialExecutor(bank)
-    Scheduler(ser).run(make_requests(48, rate=1e9, seed=99))
+    Scheduler(ser).run(make_requests(48, rate=1e9))
     st0 = Scheduler(ser).run(probe)
     mu = st0.throughput
     log(f"serving: one-at-a-time {mu:.1f} solves/s")
@@ -160,7 +294,7 @@ def run_serving(args):
         reqs = make_requests(args.requests, rate=f * mu)
         for bname, budget in budgets.items():
             ex = EngineExecutor(bank, budget, max_slots=128)
-            Scheduler(ex).run(make_requests(32, rate=1e9, seed=98))  # warm the plan pool
+            Scheduler(ex).run(make_requests(32, rate=1e9))  # warm the plan pool
             stats = Scheduler(ex).run(reqs)
             ex.close()
             runs.append(dict(rate_factor=f, executor="engine", budget=bname, p50_ms=stats.p50 * 1e3,
@@ -176,7 +310,7 @@ def run_serving(args):
     # capacity: all requests present at t = 0
     burst = make_requests(args.requests, rate=1e9)
     ex = EngineExecutor(bank, budgets["hbm"], max_slots=128)
-    Scheduler(ex).run(make_requests(32, rate=1e9, seed=98))
+    Scheduler(ex).run(make_requests(32, rate=1e9))
     stats = Scheduler(ex).run(burst)
     ex.close()
     runs.append(dict(rate_factor="burst", executor="engine", budget="hbm", p50_ms=stats.p50 * 1e3,
@@ -535,25 +669,26 @@ def run_cgsense(args):
                       "achieved_gbs": apply_bytes / apply_s / 1e9,
                       "applies_per_s": B / apply_s},
     }
-    if args.copy_calibration:
-        src = torch.ones(1 << 27, dtype=torch.complex64, device=dev)  # 1 GiB
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(5):
-            dst.copy_(src)
-        ev1.record()
-        torch.cuda.synchronize()
-        cms = ev0.elapsed_time(ev1) / 5
-        out["copy_1gib"] = {"ms": cms, "gbs_read_plus_write": 2 * (1 << 30) / cms / 1e6}
-        log(f"bench: 1 GiB copy {cms:.3f} ms ({2 * (1 << 30) / cms / 1e6:.0f} GB/s read+write)")
-        del src, dst
+    if not args.no_context:
+        out["copy_1gib"] = copy_peak(dev)
+        log(f"bench: 1 GiB copy {out['copy_1gib']['ms']:.3f} ms "
+            f"({out['copy_1gib']['gbs_read_plus_write']:.0f} GB/s read+write)")
+        lib = library_fft_ehe(maps, imgs, mask)
+        lib["note"] = "same batch, torch.fft (rocFFT), context only"
+        lib["hip_apply_ms"] = apply_s * 1e3
+        out["library_fft_ehe"] = lib
+        log(f"bench: torch.fft E^H E {lib}")
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         y0 = y[0].cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(w, maps0, mask, y0, args.cpu_seconds)
+        log(f"bench: cpu baseline {out['cpu_baseline']['value']:.2f} applies/s on "
+            f"{out['cpu_baseline']['cores']} threads")
     plan.close()
+    del maps, imgs, y, x, p, q
+    torch.cuda.empty_cache()
+    if not args.no_context:
+        out["serving"] = serving_summary()
     print(json.dumps(out), flush=True)
 
 

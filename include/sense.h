@@ -264,9 +264,17 @@ typedef struct sense_engine_s* sense_engine;
 
 SENSE_API sense_status sense_engine_create(size_t budget_bytes, int32_t max_slots, sense_engine* out);
 SENSE_API sense_status sense_engine_destroy(sense_engine engine);
+/*
+ * Admit one solve.  stream is the caller's stream on which d_y was produced
+ * and d_x was last used (NULL = the null stream): the engine's own stream
+ * waits for everything enqueued there before this admission, so the solve
+ * never reads k-space that is still being written.  The wait covers only
+ * work enqueued before the call.  Results are in d_x once poll reports the
+ * slot; the caller may then read them on any stream.
+ */
 SENSE_API sense_status sense_engine_admit(sense_engine engine, sense_plan plan, const void* d_y, void* d_x,
                                           int32_t max_iter, double rel_tol, double lambda,
-                                          size_t footprint_bytes, int32_t* slot);
+                                          size_t footprint_bytes, void* stream, int32_t* slot);
 SENSE_API sense_status sense_engine_step(sense_engine engine, int32_t* n_running);
 SENSE_API sense_status sense_engine_poll(sense_engine engine, int32_t* done_slots, int32_t max_done,
                                          int32_t* n_done);

@@ -75,7 +75,8 @@ def _load():
         lib.or_A.argtypes = dims + [P, P, P, D, P]
         lib.or_cg.argtypes = dims + [P, P, P, Ii, D, D, Ii, P, P, P, P]
         lib.or_rss.argtypes = [L, L, L, Ii, Ii, P, P]
-        for f in ("or_fft1d", "or_dft1d_direct", "or_centred1d", "or_centred_nd",
+        lib.or_set_threads.argtypes = [Ii]
+        for f in ("or_set_threads", "or_fft1d", "or_dft1d_direct", "or_centred1d", "or_centred_nd",
                   "or_E", "or_EH", "or_A", "or_cg", "or_rss"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
@@ -226,6 +227,12 @@ def rss(y, ndim=2):
     out = np.empty((batch,) + y.shape[-ndim:], dtype=np.float64)
     _check(_load().or_rss(nx, ny, nz, ncoils, batch, _ptr(y), _ptr(out)), "rss")
     return out
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the oracle's parallel loops started from the calling
+    thread (n <= 0 leaves it); returns the count in effect.  Timing only."""
+    return int(_load().or_set_threads(int(n)))
 
 
 def eq1_factor(nvox: int) -> float:

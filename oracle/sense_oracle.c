@@ -49,6 +49,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -375,6 +378,19 @@ int or_cg(long nx, long ny, long nz, int ncoils, int batch, int maps_shared,
         free(r);
     }
     return 0;
+}
+
+/* Threads of the calling thread's later parallel regions (timing only; the
+ * results do not depend on it).  Returns the threads now in effect. */
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* Root sum of squares: out[b] = sqrt( sum_c |F_c^H y[b][c]|^2 ), no mask. */

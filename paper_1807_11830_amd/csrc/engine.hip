@@ -69,6 +69,9 @@ struct sense_engine_s {
   hipStream_t lane[kLanes] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t joined[kLanes] = {};
+  // recorded on the caller's stream at admission: the engine's stream
+  // waits for it, so k-space produced there just before is complete
+  hipEvent_t admitted = nullptr;
 };
 
 static void engine_free(sense_engine e) {
@@ -90,6 +93,7 @@ static void engine_free(sense_engine e) {
     if (e->joined[i]) (void)hipEventDestroy(e->joined[i]);
   }
   if (e->fork) (void)hipEventDestroy(e->fork);
+  if (e->admitted) (void)hipEventDestroy(e->admitted);
   if (e->d_ehe) (void)hipFree(e->d_ehe);
   if (e->st) (void)hipStreamDestroy(e->st);
   delete e;
@@ -119,6 +123,7 @@ sense_status sense_engine_create(size_t budget_bytes, int32_t max_slots, sense_e
     if (err == hipSuccess) err = hipEventCreateWithFlags(&e->joined[i], hipEventDisableTiming);
   }
   if (err == hipSuccess) err = hipEventCreateWithFlags(&e->fork, hipEventDisableTiming);
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&e->admitted, hipEventDisableTiming);
   for (auto& s : e->slots)
     if (err == hipSuccess) err = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
   if (err != hipSuccess) {
@@ -138,7 +143,8 @@ sense_status sense_engine_destroy(sense_engine e) {
 }
 
 sense_status sense_engine_admit(sense_engine e, sense_plan plan, const void* d_y, void* d_x, int32_t max_iter,
-                                double rel_tol, double lambda, size_t footprint_bytes, int32_t* slot) {
+                                double rel_tol, double lambda, size_t footprint_bytes, void* stream,
+                                int32_t* slot) {
   if (!e) return fail(SENSE_ERR_INVALID, "engine is NULL");
   if (!slot) return fail(SENSE_ERR_INVALID, "slot is NULL");
   *slot = -1;
@@ -162,7 +168,11 @@ sense_status sense_engine_admit(sense_engine e, sense_plan plan, const void* d_y
 
   Slot& sl = e->slots[(size_t)free_slot];
   const CgArgs cg = plan->cg_args(rel_tol, nullptr, 0);
-  hipError_t err = enqueue_solve_begin(plan, d_y, static_cast<c32*>(d_x), cg, e->st);
+  // order the admission's work after everything the caller has enqueued
+  // on its stream so far (the producer of d_y, earlier users of d_x)
+  hipError_t err = hipEventRecord(e->admitted, static_cast<hipStream_t>(stream));
+  if (err == hipSuccess) err = hipStreamWaitEvent(e->st, e->admitted, 0);
+  if (err == hipSuccess) err = enqueue_solve_begin(plan, d_y, static_cast<c32*>(d_x), cg, e->st);
   if (err == hipSuccess && max_iter == 0) {
     err = enqueue_solve_end(plan, static_cast<c32*>(d_x), 0, cg, nullptr, e->st);
     if (err == hipSuccess) err = hipEventRecord(sl.done, e->st);

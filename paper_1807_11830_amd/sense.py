@@ -90,7 +90,7 @@ def lib():
     L.sense_plan_profile.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(D)]
     L.sense_engine_create.argtypes = [ctypes.c_size_t, I32, ctypes.POINTER(P)]
     L.sense_engine_destroy.argtypes = [P]
-    L.sense_engine_admit.argtypes = [P, P, P, P, I32, D, D, ctypes.c_size_t, ctypes.POINTER(I32)]
+    L.sense_engine_admit.argtypes = [P, P, P, P, I32, D, D, ctypes.c_size_t, P, ctypes.POINTER(I32)]
     L.sense_engine_step.argtypes = [P, ctypes.POINTER(I32)]
     L.sense_engine_poll.argtypes = [P, ctypes.POINTER(I32), I32, ctypes.POINTER(I32)]
     L.sense_engine_stats.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
@@ -390,14 +390,17 @@ class Engine:
         self._done = (ctypes.c_int32 * self.max_slots)()
 
     def admit(self, plan: Plan, y: torch.Tensor, x: torch.Tensor, max_iter: int, tol: float = 0.0,
-              lam: float = 0.0, footprint: int = 0):
-        """Slot index, or None when no slot or budget is free right now."""
+              lam: float = 0.0, footprint: int = 0, stream=None):
+        """Slot index, or None when no slot or budget is free right now.
+
+        The engine orders the solve after the work already enqueued on
+        ``stream`` (default: torch's current stream), where y was produced."""
         plan._ksp(y, "y")
         plan._img(x, "x")
         slot = ctypes.c_int32(-1)
         with torch.cuda.device(self.device):
             rc = lib().sense_engine_admit(self._h, plan._h, _ptr(y), _ptr(x), int(max_iter), float(tol),
-                                          float(lam), int(footprint), ctypes.byref(slot))
+                                          float(lam), int(footprint), _stream(stream), ctypes.byref(slot))
         if rc == 5:  # SENSE_ERR_STATE: full or over budget -> try again later
             msg = lib().sense_last_error().decode()
             if "no free slot" in msg or "budget" in msg:

@@ -37,6 +37,7 @@ class Request:
     ncoils: int
     accel: int
     iters: int
+    seed: int | None = None  # inputs drawn from this seed (None: per-class inputs)
     payload: Any = None
     admitted: float = math.nan
     finished: float = math.nan
@@ -111,10 +112,17 @@ def stats(requests, max_inflight=0, steps=0) -> RunStats:
 # ---------------------------------------------------------------------------
 
 class InputBank:
-    """Seeded synthetic inputs per request class, resident on the GPU:
-    maps per (n, coils), mask per (n, accel), k-space y = E x + noise per
-    (n, coils, accel).  Requests of one class share these read-only inputs
-    and get their own plan state and output."""
+    """Seeded synthetic inputs, resident on the GPU.
+
+    Every request of a stream carries its own sub-seed (SeedSequence
+    children of the stream seed): its coil maps are the Gaussian-bump set
+    rotated by an angle drawn from that seed, its image is a phantom drawn
+    from it and its noise is drawn from it, so every request in flight reads
+    its own maps and k-space buffers (no request shares an input buffer with
+    another).  The mask is the variable-density mask of the request's
+    (size, acceleration) class.  Requests without a seed (hand-made test
+    requests) use per-class inputs: maps per (n, coils), k-space per
+    (n, coils, accel)."""
 
     def __init__(self, device="cuda:0", n_centre=24):
         import torch
@@ -126,6 +134,12 @@ class InputBank:
         self.device = torch.device(device)
         self.n_centre = n_centre
         self.maps, self.masks, self.y = {}, {}, {}
+        self.req = {}  # (seed, n, coils, accel) -> (maps, y) of one seeded request
+        self.eplans = {}  # (n, coils, accel) -> plan that forms y = E x
+
+    @staticmethod
+    def _key(r):
+        return (r.seed, r.n, r.ncoils, r.accel)
 
     def mask(self, n, accel):
         k = (n, accel)
@@ -140,25 +154,85 @@ class InputBank:
             self.maps[k] = self.torch.from_numpy(m).to(self.device)
         return self.maps[k]
 
-    def kspace(self, n, c, accel):
+    def _kspace_of(self, maps, img, noise, n, accel):
         from .sense import Plan
 
+        torch = self.torch
+        mask = self.mask(n, accel)
+        k = (n, maps.shape[0], accel)
+        if k not in self.eplans:
+            self.eplans[k] = Plan(maps, mask)
+        plan = self.eplans[k]
+        plan.set_maps(maps)
+        y = plan.E(img)
+        y += torch.from_numpy(noise * mask[None, None, :, None]).to(self.device)
+        return y
+
+    def kspace(self, n, c, accel):
         k = (n, c, accel)
         if k not in self.y:
-            torch = self.torch
-            img = torch.from_numpy(self.synth.phantom2d(n).astype(np.complex64)[None]).to(self.device)
-            mask = self.mask(n, accel)
-            with Plan(self.coil_maps(n, c), mask) as plan:
-                y = plan.E(img)
+            img = self.torch.from_numpy(self.synth.phantom2d(n).astype(np.complex64)[None]).to(self.device)
             noise = self.synth.complex_noise((1, c, n, n)).astype(np.complex64)
-            y += torch.from_numpy(noise * mask[None, None, :, None]).to(self.device)
-            self.y[k] = y
+            self.y[k] = self._kspace_of(self.coil_maps(n, c), img, noise, n, accel)
         return self.y[k]
 
+    def _draw(self, r):
+        """Host arrays of request r from its own seed (maps, image, noise)."""
+        rng = np.random.default_rng(r.seed)
+        rot = float(rng.uniform(0.0, 2.0 * np.pi))
+        maps = self.synth.coil_maps2d(r.n, r.ncoils, rotation=rot).astype(np.complex64)
+        img = self.synth.phantom2d(r.n, seed=int(rng.integers(0, 2**31))).astype(np.complex64)[None]
+        noise = self.synth.complex_noise((1, r.ncoils, r.n, r.n), seed=int(rng.integers(0, 2**31)))
+        return maps, img, noise.astype(np.complex64)
+
+    def inputs(self, r):
+        """(maps, y) of request r on the GPU."""
+        if r.seed is None:
+            return self.coil_maps(r.n, r.ncoils), self.kspace(r.n, r.ncoils, r.accel)
+        if self._key(r) not in self.req:
+            self._make([r])
+        return self.req[self._key(r)]
+
+    def _make(self, reqs):
+        import concurrent.futures as cf
+
+        torch = self.torch
+        todo, seen = [], set()
+        for r in reqs:
+            if r.seed is not None and self._key(r) not in self.req and self._key(r) not in seen:
+                seen.add(self._key(r))
+                todo.append(r)
+        # numpy draws run in a thread pool (they release the GIL); uploads
+        # and the forward model run here, in request order
+        with cf.ThreadPoolExecutor(max_workers=8) as ex:
+            for r, (m, img, noise) in zip(todo, ex.map(self._draw, todo)):
+                maps = torch.from_numpy(m).to(self.device)
+                y = self._kspace_of(maps, torch.from_numpy(img).to(self.device), noise, r.n, r.accel)
+                self.req[self._key(r)] = (maps, y)
+
     def prepare(self, requests):
+        self._make(list(requests))
         for r in requests:
-            self.kspace(r.n, r.ncoils, r.accel)
+            if r.seed is None:
+                self.kspace(r.n, r.ncoils, r.accel)
         self.torch.cuda.synchronize()
+
+    def drop(self, requests):
+        """Free the per-request inputs of these requests."""
+        for r in requests:
+            self.req.pop(self._key(r), None)
+
+    def close(self):
+        for p in self.eplans.values():
+            p.close()
+        self.eplans.clear()
+
+    def nbytes(self):
+        """Device bytes of all resident inputs."""
+        tot = 0
+        for m, y in self.req.values():
+            tot += m.numel() * m.element_size() + y.numel() * y.element_size()
+        return tot
 
 
 class PlanPool:
@@ -171,11 +245,10 @@ class PlanPool:
         self.idle = defaultdict(list)
         self.created = 0
 
-    def get(self, r):
+    def get(self, r, maps):
         from .sense import Plan
 
         key = (r.n, r.ncoils, r.accel)
-        maps = self.bank.coil_maps(r.n, r.ncoils)
         if self.idle[key]:
             plan = self.idle[key].pop()
             plan.set_maps(maps)
@@ -194,8 +267,8 @@ class PlanPool:
 
 
 def footprint(r, plan_bytes: int) -> int:
-    """Device bytes a request holds while admitted: its plan, its k-space
-    and maps (C images each) and its output image."""
+    """Device bytes a request holds while admitted: its plan, its own
+    k-space and maps (C images each) and its output image."""
     return plan_bytes + 8 * r.n * r.n * (2 * r.ncoils + 1)
 
 
@@ -215,9 +288,10 @@ class EngineExecutor:
         st = self.engine.stats()
         if len(self.slot_req) >= self.engine.max_slots or st["used"] + fp > st["budget"]:
             return False
-        plan = self.pool.get(r)
+        maps, y = self.bank.inputs(r)
+        plan = self.pool.get(r, maps)
         x = torch.empty((1, r.n, r.n), dtype=torch.complex64, device=self.bank.device)
-        slot = self.engine.admit(plan, self.bank.kspace(r.n, r.ncoils, r.accel), x, r.iters, footprint=fp)
+        slot = self.engine.admit(plan, y, x, r.iters, footprint=fp)
         if slot is None:
             self.pool.put(r, plan)
             return False
@@ -244,11 +318,14 @@ class EngineExecutor:
 
 
 class SerialExecutor:
-    """One solve at a time through Plan.cg (the plain path)."""
+    """One solve at a time through Plan.cg (the plain path).  Every request
+    brings new buffers, so a captured whole-solve graph would be captured
+    again for each one; the solves are launched eagerly instead."""
 
-    def __init__(self, bank: InputBank):
+    def __init__(self, bank: InputBank, graphs: bool = False):
         self.bank = bank
         self.pool = PlanPool(bank)
+        self.graphs = graphs
         self.cur = None
         self.event = None
 
@@ -256,9 +333,11 @@ class SerialExecutor:
         torch = self.bank.torch
         if self.cur is not None:
             return False
-        plan = self.pool.get(r)
+        maps, y = self.bank.inputs(r)
+        plan = self.pool.get(r, maps)
+        plan.set_graphs(self.graphs)
         x = torch.empty((1, r.n, r.n), dtype=torch.complex64, device=self.bank.device)
-        plan.cg(self.bank.kspace(r.n, r.ncoils, r.accel), r.iters, out=x, sync=False)
+        plan.cg(y, r.iters, out=x, sync=False)
         self.event = torch.cuda.Event()
         self.event.record()
         r.payload = (plan, x)
@@ -291,5 +370,5 @@ def make_requests(n_requests, rate, iters=25, seed=None, **kw):
     kw = dict(kw)
     if seed is not None:
         kw["seed"] = seed
-    return [Request(d["id"], d["arrival"], d["n"], d["ncoils"], d["accel"], iters)
+    return [Request(d["id"], d["arrival"], d["n"], d["ncoils"], d["accel"], iters, seed=d["seed"])
             for d in synth.request_stream(n_requests, rate, **kw)]

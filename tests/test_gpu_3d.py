@@ -150,3 +150,35 @@ def test_autograd_gradient(shape):
             an = float(np.vdot(g.ravel(), d.ravel()).real)
             log(f"FD {fd:.6e} analytic {an:.6e}")
             assert abs(fd - an) <= 1e-3 * abs(an)
+
+
+def test_3d_full_transform_lengths_match_oracle():
+    """The differentiation workload's transform lengths (ny = 256, nz = 128,
+    (ky, kz) mask R = 6 with a 32 x 32 centre) on a narrow readout (nx = 16)
+    and 2 coils: E, E^H, E^H E and a 4-iteration CG against the oracle, so
+    the 256-point y passes and the 128-point z passes that the full volume
+    runs are all compared."""
+    nz, ny, nx, nc = 128, 256, 16, 2
+    maps = c64(synth.coil_maps3d(nx, ny, nz, nc))
+    mask = synth.mask_variable_density_2d(ny, nz, 6.0, (32, 32))
+    xt = c64(synth.phantom3d(nx, ny, nz)[None])
+    yin = c64(synth.complex_normal((1, nc, nz, ny, nx), 51))
+    log(f"3D full lengths nz={nz} ny={ny} nx={nx} C={nc}")
+    with sense.Plan(to_dev(maps), mask) as plan:
+        y = to_host(plan.E(to_dev(xt)))
+        xh = to_host(plan.EH(to_dev(yin)))
+        q = to_host(plan.EHE(to_dev(xt)))
+        yo = oracle.E(xt, maps, mask, ndim=3)
+        e1 = rel_l2(y, yo)
+        e2 = rel_l2(xh, oracle.EH(yin, maps, mask, ndim=3))
+        e3 = rel_l2(q, oracle.A(xt, maps, mask, ndim=3))
+        log(f"  E {e1:.3e} EH {e2:.3e} EHE {e3:.3e}")
+        assert max(e1, e2, e3) <= TOL_FP32
+        assert np.all(y[:, :, mask == 0, :] == 0)
+        yd = c64(yo + synth.complex_noise(yo.shape) * mask[None, None, :, :, None])
+        xo, it, st, hist = oracle.cg(yd, maps, mask, 4, ndim=3)
+        res = plan.cg(to_dev(yd), 4, history=True)
+    err = rel_l2(to_host(res.x), xo)
+    log(f"  CG (4 iterations) rel-L2 {err:.3e}")
+    assert err <= TOL_FP32 and res.iters[0] == 4
+    assert np.allclose(res.rho_hist.cpu().numpy()[0], hist[0], rtol=1e-5)

@@ -1,7 +1,9 @@
 """Serving engine on the GPU: each request's result is bitwise the same
 solved alone (Plan.cg) and in a continuously batched mix of sizes, coil
 counts and accelerations; budget and slot admission; plans in a slot are
-locked; one mixed request against the FP64 oracle."""
+locked; admission is ordered after the caller's stream; mixed requests of
+different sizes and coil counts, each with its own seeded inputs, against
+the FP64 oracle."""
 import numpy as np
 import pytest
 import torch
@@ -18,8 +20,9 @@ CLASSES = [(128, 8, 2), (192, 16, 3), (256, 8, 4), (128, 8, 2), (320, 16, 2), (1
 
 
 def _alone(bank, r):
-    with sense.Plan(bank.coil_maps(r.n, r.ncoils), bank.mask(r.n, r.accel)) as p:
-        res = p.cg(bank.kspace(r.n, r.ncoils, r.accel), r.iters)
+    maps, y = bank.inputs(r)
+    with sense.Plan(maps, bank.mask(r.n, r.accel)) as p:
+        res = p.cg(y, r.iters)
         return res.x.clone(), res.iters[0], res.status[0]
 
 
@@ -85,27 +88,45 @@ def test_mixed_storage_groups_bitwise():
     assert not torch.equal(outs[0], outs[1])  # the storages really differ
 
 
-def test_mixed_request_matches_oracle():
+def test_mixed_requests_match_oracle():
+    """A continuously batched stream of seeded requests (every request with
+    its own maps, image and noise); three of them with different sizes and
+    coil counts are checked against the oracle's CG, and every request is
+    bitwise its plain solve."""
     bank = InputBank()
-    reqs = make_requests(10, rate=5000.0, iters=10, sizes=(128, 192), coils=(8,), accels=(2, 3))
+    reqs = make_requests(14, rate=4000.0, iters=10, sizes=(128, 192, 256), coils=(8, 16), accels=(2, 3, 4))
     bank.prepare(reqs)
-    ex = EngineExecutor(bank, budget_bytes=4 << 30, max_slots=6)
-    Scheduler(ex).run(reqs)
+    # distinct inputs per request: no two requests share a maps or k-space buffer
+    ptrs = {bank.inputs(r)[0].data_ptr() for r in reqs} | {bank.inputs(r)[1].data_ptr() for r in reqs}
+    assert len(ptrs) == 2 * len(reqs)
+    alone = {r.id: _alone(bank, r)[0] for r in reqs}
+    ex = EngineExecutor(bank, budget_bytes=4 << 30, max_slots=8)
+    st = Scheduler(ex).run(reqs)
     ex.close()
-    r = reqs[-1]
-    maps = bank.coil_maps(r.n, r.ncoils).cpu().numpy().astype(np.complex128)
-    y = to_host(bank.kspace(r.n, r.ncoils, r.accel))
-    xo, _, _, _ = oracle.cg(y, maps, bank.mask(r.n, r.accel), r.iters)
-    err = rel_l2(to_host(r.result), xo)
-    log(f"request {r.id} ({r.n}, {r.ncoils}, R{r.accel}) vs oracle {err:.3e}")
-    assert err <= TOL_FP32
+    assert st.max_inflight >= 2
+    for r in reqs:
+        assert torch.equal(r.result, alone[r.id]), r
+    picks, seen = [], set()
+    for r in reversed(reqs):
+        if (r.n, r.ncoils) not in seen:
+            seen.add((r.n, r.ncoils))
+            picks.append(r)
+    picks = picks[:3]
+    assert len({p.n for p in picks}) >= 2 and len({p.ncoils for p in picks}) >= 2, picks
+    for r in picks:
+        maps, y = bank.inputs(r)
+        xo, _, _, _ = oracle.cg(to_host(y), maps.cpu().numpy().astype(np.complex128), bank.mask(r.n, r.accel),
+                                r.iters)
+        err = rel_l2(to_host(r.result), xo)
+        log(f"request {r.id} ({r.n}, {r.ncoils} coils, R{r.accel}) vs oracle {err:.3e}")
+        assert err <= TOL_FP32
 
 
 def test_engine_admission_limits():
     bank = InputBank()
     r = Request(0, 0.0, 128, 8, 2, 5)
     bank.prepare([r])
-    maps, mask, y = bank.coil_maps(128, 8), bank.mask(128, 2), bank.kspace(128, 8, 2)
+    (maps, y), mask = bank.inputs(r), bank.mask(128, 2)
     with sense.Engine(budget_bytes=1000, max_slots=2) as eng, sense.Plan(maps, mask) as p1, \
             sense.Plan(maps, mask) as p2, sense.Plan(maps, mask) as p3:
         x1, x2, x3 = (torch.empty((1, 128, 128), dtype=torch.complex64, device="cuda:0") for _ in range(3))
@@ -125,3 +146,36 @@ def test_engine_admission_limits():
         assert eng.stats()["used"] == 0
         ref = p3.cg(y, 5).x
         assert torch.equal(x1, ref) and torch.equal(x2, ref)
+
+
+def test_admit_waits_for_the_callers_stream():
+    """k-space produced on the caller's stream immediately before admission
+    (no synchronisation in between, on a non-default stream behind a long
+    queue of work) is what the engine solves: the result is bitwise the
+    plain solve's."""
+    bank = InputBank()
+    r = Request(0, 0.0, 256, 16, 3, 8)
+    bank.prepare([r])
+    maps, mask = bank.coil_maps(256, 16), bank.mask(256, 3)
+    img = torch.from_numpy(np.stack([bank.synth.phantom2d(256, seed=5)]).astype(np.complex64)).to("cuda:0")
+    with sense.Plan(maps, mask) as pe, sense.Plan(maps, mask) as pref:
+        yref = pref.E(img)
+        ref = pref.cg(yref, 8).x.clone()
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        x = torch.empty((1, 256, 256), dtype=torch.complex64, device="cuda:0")
+        with sense.Engine(budget_bytes=1 << 32, max_slots=2) as eng:
+            with torch.cuda.stream(s):
+                busy = torch.randn((4096, 4096), device="cuda:0")
+                for _ in range(8):
+                    busy = busy @ busy * 1e-3  # keep the caller's stream busy
+                y = torch.zeros_like(yref)
+                y += yref  # y is ready only after the queue above
+                assert eng.admit(pe, y, x, 8) == 0
+            done = []
+            while not done:
+                eng.step()
+                done = eng.poll()
+            eng.sync()
+        torch.cuda.synchronize()
+    assert torch.equal(x, ref)
