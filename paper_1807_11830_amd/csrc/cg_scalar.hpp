@@ -42,20 +42,24 @@ __device__ __forceinline__ bool cg_iteration_begin(CgState* st, const double* rr
 }
 
 // Fused 2D CG: launch k (k >= 1) finishes iteration k-1 before applying A.
-// From the partials of launch k-1 (eta = Re<p,q>, xi = Re<r,q>, zeta =
-// <q,q>, rho = <r,r>, the true residual norm of iterate k-1) it checks, in
-// the order of the textbook loop, rho (non-finite; tolerance; exactly 0) and
-// eta (non-finite; <= 0), then sets alpha = rho / eta and beta = rho~ / rho
-// with rho~ = rho - 2 alpha xi + alpha^2 zeta = <r - alpha q, r - alpha q>.
+// From the partials of launch k-1 (eta = Re<p,q>, zeta = <q,q>, rho =
+// <r,r>, the true residual norm of iterate k-1) it checks, in the order of
+// the textbook loop, rho (non-finite; tolerance; exactly 0) and eta
+// (non-finite; <= 0), then sets alpha = rho / eta and beta = rho~ / rho with
+//     rho~ = <r - alpha q, r - alpha q> = rho - 2 alpha Re<r,q> + alpha^2 zeta
+//          = alpha^2 zeta - rho,
+// the last form because Re<r, A p> = Re<p, A p> = eta: the direction is
+// p = r + beta' p_prev and A-conjugate to p_prev, and alpha eta = rho.
 // rho~ serves only for beta; the true <r, r> of the new residual is
-// computed by this launch and used from the next launch on.  Launch 0 only
-// checks rho_0 (from the init kernel) and leaves alpha = beta = 0.
+// computed by this launch and used from the next launch on, so no error
+// accumulates through it.  Launch 0 only checks rho_0 (from the init kernel)
+// and leaves alpha = beta = 0.
 struct CgFused {
   double alpha, beta;
 };
 
 __device__ __forceinline__ bool cg_fused_begin(CgState* st, const double* rr_part, int rr_tiles,
-                                               const double* part4, int part_batch, int ntiles,
+                                               const double* cgpart, int part_batch, int ntiles,
                                                double* rho_hist, int hist_len, double tol, int k, int b,
                                                bool designated, CgFused& o) {
   o.alpha = 0.0;
@@ -75,13 +79,12 @@ __device__ __forceinline__ bool cg_fused_begin(CgState* st, const double* rr_par
     }
     return stop == CG_RUNNING;
   }
-  const double* pp = part4 + ((long)((k - 1) & 1) * part_batch + b) * (long)ntiles * 4;
-  double eta = 0.0, xi = 0.0, zeta = 0.0, rho = 0.0;
+  const double* pp = cgpart + ((long)((k - 1) & 1) * part_batch + b) * (long)ntiles * kCgParts;
+  double eta = 0.0, zeta = 0.0, rho = 0.0;
   for (int i = 0; i < ntiles; ++i) {
-    eta += pp[4 * i];
-    xi += pp[4 * i + 1];
-    zeta += pp[4 * i + 2];
-    rho += pp[4 * i + 3];
+    eta += pp[kCgParts * i];
+    zeta += pp[kCgParts * i + 1];
+    rho += pp[kCgParts * i + 2];
   }
   int stop = CG_RUNNING;
   if (!finite64(rho)) stop = CG_NONFINITE;
@@ -98,7 +101,7 @@ __device__ __forceinline__ bool cg_fused_begin(CgState* st, const double* rr_par
   }
   if (stop != CG_RUNNING) return false;
   o.alpha = rho / eta;
-  const double rho_next = rho - 2.0 * o.alpha * xi + o.alpha * o.alpha * zeta;
+  const double rho_next = o.alpha * o.alpha * zeta - rho;
   o.beta = rho_next / rho;
   return true;
 }

@@ -64,15 +64,19 @@ struct Tables {
   int n_rows_u;
 };
 
+// fp64 partials a fused 2D CG launch leaves per block: Re<p, q>, <q, q>
+// and <r, r> (in that order).
+constexpr int kCgParts = 3;
+
 struct CgArgs {
   CgState* state;        // [B]
   double* eta_part;      // [B][eta_tiles]
   double* rr_part;       // [B][rr_tiles]
   int eta_tiles;
   int rr_tiles;
-  // fused 2D iteration: [2][B][part_tiles][4] partials (Re<p,q>, Re<r,q>,
+  // fused 2D iteration: [2][B][part_tiles][kCgParts] partials (Re<p,q>,
   // <q,q>, <r,r>), double-buffered by iteration parity
-  double* part4;
+  double* cgpart;
   int part_tiles;
   int part_batch;
   double* rho_hist;      // optional [B][hist_len]
@@ -117,9 +121,9 @@ struct EheParams {
   CgState* state;
   const double* rr_part;
   int rr_tiles;
-  double* part4;
+  double* cgpart;
   int part_batch;
-  int part_tiles;    // tiles of the part4 layout (ntiles for G = 1, cg_tiles(nvox) for G > 1)
+  int part_tiles;    // tiles of the cgpart layout (ntiles for G = 1, cg_tiles(nvox) for G > 1)
   int k;             // iteration index of this launch
   double* rho_hist;
   int hist_len;

@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(CG_NT) cg_fused_final_kernel(c32* __restrict__
   __shared__ double red[CG_NT / 64];
   const int b = blockIdx.y;
   CgFused o;
-  if (!cg_fused_begin(cg.state + b, cg.rr_part, cg.rr_tiles, cg.part4, cg.part_batch, cg.part_tiles,
+  if (!cg_fused_begin(cg.state + b, cg.rr_part, cg.rr_tiles, cg.cgpart, cg.part_batch, cg.part_tiles,
                       cg.rho_hist, cg.hist_len, cg.tol, K, b, blockIdx.x == 0 && threadIdx.x == 0, o))
     return;
   const double alpha = o.alpha;
@@ -229,8 +229,8 @@ hipError_t launch_cg_fused_final(const Geom& g, const CgVectors& v, int K, const
 
 // Coil-group combine of one problem row: q = sum_g qpart[g] + lambda p, the
 // groups added in index order (no lambda p when p is null: the E^H combine).
-// CG mode (P.state set) also emits the fp64 partials Re<p,q>, Re<r,q>,
-// <q,q>, <r,r> of launch k into part4[k & 1] (one entry per block of this
+// CG mode (P.state set) also emits the fp64 partials Re<p,q>, <q,q> and
+// <r,r> of launch k into cgpart[k & 1] (one entry per block of this
 // kernel) and skips a problem that has stopped.  GB >= G slots: the loads of
 // SU accesses (every group partial, p and r) are all issued before the first
 // add, so a thread waits for memory once per SU accesses rather than once
@@ -253,7 +253,7 @@ __device__ __forceinline__ void combine_body(const EheParams& P, const int b, co
   const Buf bg = make_buf(P.qpart, (uint32_t)((long)G * P.qpart_gstride * (long)sizeof(c32)));
   const Buf bp = make_buf(pk, pk ? vbytes : 0u);
   const Buf br = make_buf(P.r_out, cg ? vbytes : 0u);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[kCgParts] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int s0 = 0; s0 < CG_STEPS; s0 += SU) {
     c32x2 t[SU][GB], pv[SU], rv[SU];
@@ -295,19 +295,17 @@ __device__ __forceinline__ void combine_body(const EheParams& P, const int b, co
         const c32x2 r = rv[u];
         acc[0] += (double)p.a.re * qv.a.re + (double)p.a.im * qv.a.im + (double)p.b.re * qv.b.re +
                   (double)p.b.im * qv.b.im;
-        acc[1] += (double)r.a.re * qv.a.re + (double)r.a.im * qv.a.im + (double)r.b.re * qv.b.re +
-                  (double)r.b.im * qv.b.im;
-        acc[2] += (double)qv.a.re * qv.a.re + (double)qv.a.im * qv.a.im + (double)qv.b.re * qv.b.re +
+        acc[1] += (double)qv.a.re * qv.a.re + (double)qv.a.im * qv.a.im + (double)qv.b.re * qv.b.re +
                   (double)qv.b.im * qv.b.im;
-        acc[3] += (double)r.a.re * r.a.re + (double)r.a.im * r.a.im + (double)r.b.re * r.b.re +
+        acc[2] += (double)r.a.re * r.a.re + (double)r.a.im * r.a.im + (double)r.b.re * r.b.re +
                   (double)r.b.im * r.b.im;
       }
     }
   }
   if (!cg) return;
-  double* out = P.part4 + (((long)(P.k & 1) * P.part_batch + b) * P.part_tiles + tile) * 4;
+  double* out = P.cgpart + (((long)(P.k & 1) * P.part_batch + b) * P.part_tiles + tile) * kCgParts;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < kCgParts; ++i) {
     const double tot = block_sum<CG_NT>(acc[i], red);
     if (threadIdx.x == 0) out[i] = tot;
     __syncthreads();  // red is reused

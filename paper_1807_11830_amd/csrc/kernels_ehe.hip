@@ -91,7 +91,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   // CG: the start-of-iteration scalars (every block derives the same ones)
   [[maybe_unused]] CgFused cgs{};
   if constexpr (CG) {
-    if (!cg_fused_begin(P.state + b, P.rr_part, P.rr_tiles, P.part4, P.part_batch, P.part_tiles, P.rho_hist,
+    if (!cg_fused_begin(P.state + b, P.rr_part, P.rr_tiles, P.cgpart, P.part_batch, P.part_tiles, P.rho_hist,
                         P.hist_len, P.tol, P.k, b, tile == 0 && grp == 0 && tid == 0, cgs))
       return;
   }
@@ -291,31 +291,21 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
       if (tid == 0) P.eta_part[(long)b * P.ntiles + tile] = tot;
     }
   } else {
-    // q = A p; fp64 partials of Re<p,q>, Re<r,q>, <q,q>, <r,r> for the
-    // next launch (alpha, the recurrence for beta, and the true rho_k)
-    double acc[4] = {0.0, 0.0, 0.0, rho_acc};
-    // the residual written by the prologue, re-read rather than kept in
-    // registers across the transforms (all loads before the first q store,
-    // so no wait covers a store)
-    c32 rr[E];
-    const Buf brr = make_buf(P.r_out + (long)b * nvox, img_bytes);
-#pragma unroll
-    for (int j = 0; j < E; ++j) rr[j] = buf_load_c64(brr, voff * 8u, (uint32_t)j * rstep * 8u);
-    asm volatile("" ::: "memory");
+    // q = A p; fp64 partials of Re<p,q>, <q,q> and <r,r> (the new
+    // residual, summed in the prologue) for the next launch
+    double acc[kCgParts] = {0.0, 0.0, rho_acc};
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       c32 qq = {q[j].re + P.lambda * p[j].re, q[j].im + P.lambda * p[j].im};
-      const c32 rv = rr[j];
       if (valid) {
         buf_store_c64(bq, qq, voff * 8u, (uint32_t)j * rstep * 8u);
         acc[0] += (double)p[j].re * (double)qq.re + (double)p[j].im * (double)qq.im;
-        acc[1] += (double)rv.re * (double)qq.re + (double)rv.im * (double)qq.im;
-        acc[2] += (double)qq.re * (double)qq.re + (double)qq.im * (double)qq.im;
+        acc[1] += (double)qq.re * (double)qq.re + (double)qq.im * (double)qq.im;
       }
     }
-    double* out = P.part4 + (((long)(P.k & 1) * P.part_batch + b) * P.part_tiles + tile) * 4;
+    double* out = P.cgpart + (((long)(P.k & 1) * P.part_batch + b) * P.part_tiles + tile) * kCgParts;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kCgParts; ++i) {
       const double tot = block_sum<NT>(acc[i], red);
       if (tid == 0) out[i] = tot;
       if constexpr (NT / 64 > 1) __syncthreads();  // red is reused
@@ -470,7 +460,7 @@ void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, const
   P.state = cg.state;
   P.rr_part = cg.rr_part;
   P.rr_tiles = cg.rr_tiles;
-  P.part4 = cg.part4;
+  P.cgpart = cg.cgpart;
   P.part_batch = cg.part_batch;
   P.part_tiles = cg.part_tiles;
   P.rho_hist = cg.rho_hist;

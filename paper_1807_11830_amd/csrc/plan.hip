@@ -97,7 +97,7 @@ static Layout make_layout(const sense_desc& d) {
   L.eta_part = take(sizeof(double) * B * (size_t)L.eta_tiles);
   L.rr_part = take(sizeof(double) * B * (size_t)L.rr_tiles);
   const size_t ptiles = (size_t)std::max(L.eta_tiles, L.rr_tiles);
-  L.part4 = take(sizeof(double) * 2 * B * ptiles * 4);
+  L.cgpart = take(sizeof(double) * 2 * B * ptiles * kCgParts);
   L.info = take(sizeof(CgInfo) * B);
   L.total = off;
   return L;

@@ -14,7 +14,7 @@ namespace sense {
 struct Layout {
   size_t tw_x, tw_y, tw_z, mu_y, mask_c, rows_s, rows_u;
   size_t work, r, p, q, r2, p2, qpart;
-  size_t state, eta_part, rr_part, part4, info;
+  size_t state, eta_part, rr_part, cgpart, info;
   size_t total;
   int eta_tiles, rr_tiles;
   int ngroups;   // coil groups the workspace holds (the fill split)
@@ -94,7 +94,7 @@ struct sense_plan_s {
     a.rr_part = at<double>(L.rr_part);
     a.eta_tiles = L.eta_tiles;
     a.rr_tiles = L.rr_tiles;
-    a.part4 = at<double>(L.part4);
+    a.cgpart = at<double>(L.cgpart);
     a.part_tiles = ngroups > 1 ? L.rr_tiles : L.eta_tiles;
     a.part_batch = d.batch;
     a.rho_hist = hist;
