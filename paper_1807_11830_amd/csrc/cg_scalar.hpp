@@ -59,7 +59,8 @@ struct CgFused {
 };
 
 __device__ __forceinline__ bool cg_fused_begin(CgState* st, const double* rr_part, int rr_tiles,
-                                               const double* cgpart, int part_batch, int ntiles,
+                                               const double* cgpart, int part_batch, int ntiles, int rho_tiles,
+                                               int stride,
                                                double* rho_hist, int hist_len, double tol, int k, int b,
                                                bool designated, CgFused& o) {
   o.alpha = 0.0;
@@ -79,13 +80,13 @@ __device__ __forceinline__ bool cg_fused_begin(CgState* st, const double* rr_par
     }
     return stop == CG_RUNNING;
   }
-  const double* pp = cgpart + ((long)((k - 1) & 1) * part_batch + b) * (long)ntiles * kCgParts;
+  const double* pp = cgpart + ((long)((k - 1) & 1) * part_batch + b) * (long)stride * kCgParts;
   double eta = 0.0, zeta = 0.0, rho = 0.0;
   for (int i = 0; i < ntiles; ++i) {
     eta += pp[kCgParts * i];
     zeta += pp[kCgParts * i + 1];
-    rho += pp[kCgParts * i + 2];
   }
+  for (int i = 0; i < rho_tiles; ++i) rho += pp[kCgParts * i + 2];
   int stop = CG_RUNNING;
   if (!finite64(rho)) stop = CG_NONFINITE;
   else if (k - 1 > 0 && tol > 0.0 && sqrt(rho / st->rho0) < tol) stop = CG_CONVERGED;

@@ -74,10 +74,16 @@ struct CgArgs {
   double* rr_part;       // [B][rr_tiles]
   int eta_tiles;
   int rr_tiles;
-  // fused 2D iteration: [2][B][part_tiles][kCgParts] partials (Re<p,q>,
-  // <q,q>, <r,r>), double-buffered by iteration parity
+  // fused 2D iteration: [2][B][part_stride][kCgParts] partials (Re<p,q>,
+  // <q,q>, <r,r>), double-buffered by iteration parity.  Re<p,q> and <q,q>
+  // come from the blocks that form q (part_tiles of them: the fused kernel's
+  // column tiles with one coil group, the combine pass's tiles with
+  // several); <r,r> from the blocks that update r (rho_tiles: the column
+  // tiles of the fused kernel, coil group 0).
   double* cgpart;
   int part_tiles;
+  int rho_tiles;
+  int part_stride;
   int part_batch;
   double* rho_hist;      // optional [B][hist_len]
   int hist_len;
@@ -123,7 +129,9 @@ struct EheParams {
   int rr_tiles;
   double* cgpart;
   int part_batch;
-  int part_tiles;    // tiles of the cgpart layout (ntiles for G = 1, cg_tiles(nvox) for G > 1)
+  int part_tiles;    // blocks leaving Re<p,q>, <q,q> (ntiles for G = 1, cg_tiles(nvox) for G > 1)
+  int rho_tiles;     // blocks leaving <r,r> (ntiles)
+  int part_stride;   // entries per batch element of the cgpart layout
   int k;             // iteration index of this launch
   double* rho_hist;
   int hist_len;

@@ -186,6 +186,7 @@ __global__ void __launch_bounds__(CG_NT) cg_fused_final_kernel(c32* __restrict__
   const int b = blockIdx.y;
   CgFused o;
   if (!cg_fused_begin(cg.state + b, cg.rr_part, cg.rr_tiles, cg.cgpart, cg.part_batch, cg.part_tiles,
+                      cg.rho_tiles, cg.part_stride,
                       cg.rho_hist, cg.hist_len, cg.tol, K, b, blockIdx.x == 0 && threadIdx.x == 0, o))
     return;
   const double alpha = o.alpha;
@@ -229,11 +230,11 @@ hipError_t launch_cg_fused_final(const Geom& g, const CgVectors& v, int K, const
 
 // Coil-group combine of one problem row: q = sum_g qpart[g] + lambda p, the
 // groups added in index order (no lambda p when p is null: the E^H combine).
-// CG mode (P.state set) also emits the fp64 partials Re<p,q>, <q,q> and
-// <r,r> of launch k into cgpart[k & 1] (one entry per block of this
-// kernel) and skips a problem that has stopped.  GB >= G slots: the loads of
-// SU accesses (every group partial, p and r) are all issued before the first
-// add, so a thread waits for memory once per SU accesses rather than once
+// CG mode (P.state set) also emits the fp64 partials Re<p,q> and <q,q> of
+// launch k into cgpart[k & 1] (one entry per block of this
+// kernel; <r,r> comes from the fused kernel's group 0) and skips a problem
+// that has stopped.  GB >= G slots: the loads of SU accesses (every group
+// partial and p) are all issued before the first add, so a thread waits for memory once per SU accesses rather than once
 // per partial; groups past G and accesses past the end use an out-of-range
 // buffer offset, which reads nothing.
 template <int GB>
@@ -252,11 +253,10 @@ __device__ __forceinline__ void combine_body(const EheParams& P, const int b, co
   const uint32_t vbytes = (uint32_t)(lim * (long)sizeof(c32));
   const Buf bg = make_buf(P.qpart, (uint32_t)((long)G * P.qpart_gstride * (long)sizeof(c32)));
   const Buf bp = make_buf(pk, pk ? vbytes : 0u);
-  const Buf br = make_buf(P.r_out, cg ? vbytes : 0u);
-  double acc[kCgParts] = {0.0, 0.0, 0.0};
+  double acc[2] = {0.0, 0.0};
 #pragma unroll
   for (int s0 = 0; s0 < CG_STEPS; s0 += SU) {
-    c32x2 t[SU][GB], pv[SU], rv[SU];
+    c32x2 t[SU][GB], pv[SU];
     long idx[SU];
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
@@ -271,7 +271,6 @@ __device__ __forceinline__ void combine_body(const EheParams& P, const int b, co
       }
       const uint32_t vo = in ? (uint32_t)(i * (long)sizeof(c32)) : kBufOOB;
       pv[u] = __builtin_bit_cast(c32x2, __builtin_amdgcn_raw_buffer_load_b128(bp.r, (int)vo, 0, 0));
-      if (cg) rv[u] = __builtin_bit_cast(c32x2, __builtin_amdgcn_raw_buffer_load_b128(br.r, (int)vo, 0, 0));
     }
 #pragma unroll
     for (int u = 0; u < SU; ++u) {
@@ -292,20 +291,17 @@ __device__ __forceinline__ void combine_body(const EheParams& P, const int b, co
       qv.b = {qs.b.re + lam * p.b.re, qs.b.im + lam * p.b.im};
       *reinterpret_cast<c32x2*>(P.q + idx[u]) = qv;
       if (cg) {
-        const c32x2 r = rv[u];
         acc[0] += (double)p.a.re * qv.a.re + (double)p.a.im * qv.a.im + (double)p.b.re * qv.b.re +
                   (double)p.b.im * qv.b.im;
         acc[1] += (double)qv.a.re * qv.a.re + (double)qv.a.im * qv.a.im + (double)qv.b.re * qv.b.re +
                   (double)qv.b.im * qv.b.im;
-        acc[2] += (double)r.a.re * r.a.re + (double)r.a.im * r.a.im + (double)r.b.re * r.b.re +
-                  (double)r.b.im * r.b.im;
       }
     }
   }
   if (!cg) return;
-  double* out = P.cgpart + (((long)(P.k & 1) * P.part_batch + b) * P.part_tiles + tile) * kCgParts;
+  double* out = P.cgpart + (((long)(P.k & 1) * P.part_batch + b) * P.part_stride + tile) * kCgParts;
 #pragma unroll
-  for (int i = 0; i < kCgParts; ++i) {
+  for (int i = 0; i < 2; ++i) {
     const double tot = block_sum<CG_NT>(acc[i], red);
     if (threadIdx.x == 0) out[i] = tot;
     __syncthreads();  // red is reused

@@ -91,8 +91,9 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   // CG: the start-of-iteration scalars (every block derives the same ones)
   [[maybe_unused]] CgFused cgs{};
   if constexpr (CG) {
-    if (!cg_fused_begin(P.state + b, P.rr_part, P.rr_tiles, P.cgpart, P.part_batch, P.part_tiles, P.rho_hist,
-                        P.hist_len, P.tol, P.k, b, tile == 0 && grp == 0 && tid == 0, cgs))
+    if (!cg_fused_begin(P.state + b, P.rr_part, P.rr_tiles, P.cgpart, P.part_batch, P.part_tiles, P.rho_tiles,
+                        P.part_stride, P.rho_hist, P.hist_len, P.tol, P.k, b, tile == 0 && grp == 0 && tid == 0,
+                        cgs))
       return;
   }
 
@@ -163,7 +164,8 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     // iteration k > 0 first finishes iteration k-1:
     //   x += alpha p,  r -= alpha q,  p = r + beta p
     // Every coil group computes the new p for its own transforms; group 0
-    // stores x, r, p.
+    // stores x, r, p (the other groups do not read x: its loads take an
+    // out-of-range offset, which reads nothing).
     const Buf bp = make_buf(P.p_in + (long)b * nvox, img_bytes);
     const Buf br = make_buf(P.r + (long)b * nvox, img_bytes);
     const Buf bx = make_buf(P.x + (long)b * nvox, img_bytes);
@@ -179,6 +181,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     constexpr int G = E % 4 == 0 ? 4 : 1;
     constexpr int NG = E / G;
     const uint32_t lo = voff * 8u;
+    const uint32_t lox = owner ? lo : kBufOOB;
     const double a = cgs.alpha, bt = cgs.beta;
     c32 lp[2][G], lr[2][G], lq[2][G], lx[2][G];
     auto load_group = [&](auto gc, int slot) {
@@ -189,7 +192,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
         lp[slot][i] = buf_load_c64(bp, lo, so);
         lr[slot][i] = buf_load_c64(br, lo, so);
         lq[slot][i] = buf_load_c64(bq, lo, so);
-        lx[slot][i] = buf_load_c64(bx, lo, so);  // unconditional: keeps the waits exact
+        lx[slot][i] = buf_load_c64(bx, lox, so);  // unconditional: keeps the waits exact
       });
     };
     auto update_group = [&](auto gc, int slot) {
@@ -274,6 +277,14 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
 #pragma unroll
       for (int j = 0; j < E; ++j) buf_store_c64(bg, q[j], voff * 8u, (uint32_t)j * rstep * 8u);
     }
+    if constexpr (CG) {
+      // group 0 leaves <r,r> of the residual it stored in the prologue
+      if (grp == 0) {
+        const double tot = block_sum<NT>(rho_acc, red);
+        if (tid == 0)
+          P.cgpart[(((long)(P.k & 1) * P.part_batch + b) * P.part_stride + tile) * kCgParts + 2] = tot;
+      }
+    }
     return;
   }
   if constexpr (!CG) {
@@ -303,7 +314,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
         acc[1] += (double)qq.re * (double)qq.re + (double)qq.im * (double)qq.im;
       }
     }
-    double* out = P.cgpart + (((long)(P.k & 1) * P.part_batch + b) * P.part_tiles + tile) * kCgParts;
+    double* out = P.cgpart + (((long)(P.k & 1) * P.part_batch + b) * P.part_stride + tile) * kCgParts;
 #pragma unroll
     for (int i = 0; i < kCgParts; ++i) {
       const double tot = block_sum<NT>(acc[i], red);
@@ -463,6 +474,8 @@ void fill_ehe_cg_params(const Geom& g, const Tables& tb, const void* maps, const
   P.cgpart = cg.cgpart;
   P.part_batch = cg.part_batch;
   P.part_tiles = cg.part_tiles;
+  P.rho_tiles = cg.rho_tiles;
+  P.part_stride = cg.part_stride;
   P.rho_hist = cg.rho_hist;
   P.hist_len = cg.hist_len;
   P.tol = cg.tol;

@@ -96,6 +96,8 @@ struct sense_plan_s {
     a.rr_tiles = L.rr_tiles;
     a.cgpart = at<double>(L.cgpart);
     a.part_tiles = ngroups > 1 ? L.rr_tiles : L.eta_tiles;
+    a.rho_tiles = L.eta_tiles;
+    a.part_stride = std::max(L.eta_tiles, L.rr_tiles);
     a.part_batch = d.batch;
     a.rho_hist = hist;
     a.hist_len = hist_len;
