@@ -358,59 +358,71 @@ def precision_roofline(st, n, C, B, K, launch_s):
 
 
 def run_precision(args):
-    """384x384, 32 coils, 8 slices, VD R=4, 40 iterations: maps and k-space
-    in c64 / bf16 / fp16 storage (fp32 arithmetic, fp64 reductions); solves/s
-    and the relative L2 difference of each 16-bit result from the GPU
-    complex64 result over all slices.  The errors against the FP64 oracle are
-    the parity test's (tests/test_gpu_precision.py)."""
+    """384x384, 32 coils, VD R=4, 40 iterations: maps and k-space in c64 /
+    bf16 / fp16 storage (fp32 arithmetic, fp64 reductions), at the workload's
+    batch of 8 slices (whose BF16 working set fits the 256 MB memory-side
+    cache) and at 48 slices (which does not); solves/s, both roofline bounds
+    of the fused CG launch, and the relative L2 difference of each 16-bit
+    result from the GPU complex64 result over all slices.  The errors against
+    the FP64 oracle are the parity test's (tests/test_gpu_precision.py)."""
     import torch
 
     from paper_1807_11830_amd import sense, synth
 
     w = synth.PREC_384
-    B, K, n, C = w.batch, w.iters, w.n, w.ncoils
+    K, n, C = w.iters, w.n, w.ncoils
     dev = torch.device("cuda:0")
-    imgs, maps, mask = synth.slice_inputs(w, B, per_slice_maps=True)
-    maps_t = torch.from_numpy(maps.astype(np.complex64)).to(dev)
-    imgs_t = torch.from_numpy(imgs.astype(np.complex64)).to(dev)
-    with sense.Plan(maps_t, mask, batch=B) as p0:
-        y = p0.E(imgs_t)
-    noise = synth.complex_noise((B, C, n, n)).astype(np.complex64) * mask[None, None, :, None]
-    y += torch.from_numpy(noise).to(dev)
-    out = {}
-    xs = {}
-    for st in ("c64", "bf16", "fp16"):
-        with sense.Plan(maps_t, mask, batch=B, maps_storage=st, kspace_storage=st) as plan:
-            ys = sense.to_storage(y, st)
-            plan.cg(ys, K)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            reps = 5
-            for _ in range(reps):
+    res = {}
+    for B in (w.batch, 48):
+        imgs, maps, mask = synth.slice_inputs(w, B, per_slice_maps=True)
+        maps_t = torch.from_numpy(maps.astype(np.complex64)).to(dev)
+        imgs_t = torch.from_numpy(imgs.astype(np.complex64)).to(dev)
+        del imgs, maps
+        with sense.Plan(maps_t, mask, batch=B) as p0:
+            y = p0.E(imgs_t)
+        noise = synth.complex_noise((B, C, n, n)).astype(np.complex64) * mask[None, None, :, None]
+        y += torch.from_numpy(noise).to(dev)
+        del noise
+        out = {}
+        xs = {}
+        for st in ("c64", "bf16", "fp16"):
+            with sense.Plan(maps_t, mask, batch=B, maps_storage=st, kspace_storage=st) as plan:
+                ys = sense.to_storage(y, st)
+                plan.cg(ys, K)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                reps = 5
+                for _ in range(reps):
+                    plan.cg(ys, K, sync=False)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / reps
+                xs[st] = plan.cg(ys, K).x.clone()
+                # per-launch times of the fused CG launch (group launch + combine)
+                plan.set_profiling(True)
                 plan.cg(ys, K, sync=False)
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / reps
-            xs[st] = plan.cg(ys, K).x.clone()
-            # per-launch times of the fused CG launch (group launch + combine)
-            plan.set_profiling(True)
-            plan.cg(ys, K, sync=False)
-            torch.cuda.synchronize()
-            n_l, ms_l = plan.profile()
-            plan.set_profiling(False)
-            launch_s = ms_l / 1e3 / max(n_l, 1)
-            out[st] = {"solve_ms": dt * 1e3, "applies_per_s": B * K / dt,
-                       "fused_launch": precision_roofline(st, n, C, B, K, launch_s)}
-        log(f"precision: {st} {dt*1e3:.2f} ms/solve, fused launch {launch_s*1e6:.1f} us")
-    for st in ("bf16", "fp16"):
-        d = xs[st] - xs["c64"]
-        out[st]["rel_l2_vs_gpu_c64_max_over_slices"] = float(
-            (torch.linalg.vector_norm(d.reshape(B, -1), dim=1)
-             / torch.linalg.vector_norm(xs["c64"].reshape(B, -1), dim=1)).max())
-        log(f"precision: {st} {out[st]}")
+                torch.cuda.synchronize()
+                n_l, ms_l = plan.profile()
+                plan.set_profiling(False)
+                launch_s = ms_l / 1e3 / max(n_l, 1)
+                out[st] = {"solve_ms": dt * 1e3, "applies_per_s": B * K / dt, "coil_groups": plan.coil_groups()[0],
+                           "fused_launch": precision_roofline(st, n, C, B, K, launch_s)}
+                del ys
+            log(f"precision: B={B} {st} {dt*1e3:.2f} ms/solve, fused launch {launch_s*1e6:.1f} us, "
+                f"frac {out[st]['fused_launch']['frac']:.3f}")
+        for st in ("bf16", "fp16"):
+            d = xs[st] - xs["c64"]
+            out[st]["rel_l2_vs_gpu_c64_max_over_slices"] = float(
+                (torch.linalg.vector_norm(d.reshape(B, -1), dim=1)
+                 / torch.linalg.vector_norm(xs["c64"].reshape(B, -1), dim=1)).max())
+            out[st]["speedup_vs_c64"] = out["c64"]["solve_ms"] / out[st]["solve_ms"]
+            log(f"precision: B={B} {st} {out[st]}")
+        res[f"batch{B}"] = out
+        del maps_t, imgs_t, y, xs
+        torch.cuda.empty_cache()
     print(json.dumps({"metric": "E^H E applies/s by storage precision (CG-SENSE, 40 iterations)",
-                      "value": out["bf16"]["applies_per_s"], "unit": "applies/s", "n_gpus": 1,
+                      "value": res[f"batch{w.batch}"]["bf16"]["applies_per_s"], "unit": "applies/s", "n_gpus": 1,
                       "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-                      "config": {"workload": w.name, "slices": B, "iters": K}, "variants": out}), flush=True)
+                      "config": {"workload": w.name, "slices": w.batch, "iters": K}, "variants": res}), flush=True)
 
 
 def run_small(args):

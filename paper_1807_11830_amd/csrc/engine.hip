@@ -172,14 +172,23 @@ sense_status sense_engine_admit(sense_engine e, sense_plan plan, const void* d_y
   // on its stream so far (the producer of d_y, earlier users of d_x)
   hipError_t err = hipEventRecord(e->admitted, static_cast<hipStream_t>(stream));
   if (err == hipSuccess) err = hipStreamWaitEvent(e->st, e->admitted, 0);
-  if (err == hipSuccess) err = enqueue_solve_begin(plan, d_y, static_cast<c32*>(d_x), cg, e->st);
-  if (err == hipSuccess && max_iter == 0) {
-    err = enqueue_solve_end(plan, static_cast<c32*>(d_x), 0, cg, nullptr, e->st);
+  // a small slice runs its whole solve at admission (one launch after
+  // E^H y); the others join the batched steps
+  const bool whole = small_solve(plan);
+  if (whole) {
+    if (err == hipSuccess)
+      err = enqueue_small_solve(plan, d_y, static_cast<c32*>(d_x), max_iter, (float)lambda, cg, nullptr, e->st);
     if (err == hipSuccess) err = hipEventRecord(sl.done, e->st);
+  } else {
+    if (err == hipSuccess) err = enqueue_solve_begin(plan, d_y, static_cast<c32*>(d_x), cg, e->st);
+    if (err == hipSuccess && max_iter == 0) {
+      err = enqueue_solve_end(plan, static_cast<c32*>(d_x), 0, cg, nullptr, e->st);
+      if (err == hipSuccess) err = hipEventRecord(sl.done, e->st);
+    }
   }
   if (err != hipSuccess) return device_fail(err, "sense_engine_admit");
   sl.used = true;
-  sl.finishing = max_iter == 0;
+  sl.finishing = whole || max_iter == 0;
   sl.plan = plan;
   sl.y = d_y;
   sl.x = static_cast<c32*>(d_x);

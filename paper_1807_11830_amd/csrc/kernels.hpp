@@ -214,6 +214,13 @@ hipError_t launch_combine_inline(const EheInline& table, int nproblems, int max_
 hipError_t launch_combine(const EheParams& P, int batch, bool cg, hipStream_t st);
 
 
+// Whole CG solves of small 2D slices (nx <= 64, ny in {8, 16, 32, 48, 64},
+// one coil group): one workgroup per batch element runs all K iterations
+// from b = E^H y and writes x, the CG state, the info and the rho history.
+bool small_solve_supported(const Geom& g);
+hipError_t launch_cg_small(const Geom& g, const Tables& tb, const void* maps, const c32* bvec, c32* x, int K,
+                           float lambda, const CgArgs& cg, CgInfo* info, CgInfo* info2, hipStream_t st);
+
 // Full-grid forward and adjoint operators (2D).
 hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32* x, c32* work,
                     void* y, hipStream_t st);

@@ -204,8 +204,24 @@ hipError_t enqueue_solve_end(sense_plan p, c32* x, int K, const CgArgs& cg, CgIn
   return e;
 }
 
+bool small_solve(const sense_plan_s* p) { return p->d.ndim == 2 && p->ngroups == 1 && small_solve_supported(p->g); }
+
+// Small slices: E^H y into r, then one launch runs the whole solve.
+hipError_t enqueue_small_solve(sense_plan p, const void* d_y, c32* x, int32_t max_iter, float lambda,
+                               const CgArgs& cg, CgInfo* d_info, hipStream_t st) {
+  c32* r = p->at<c32>(p->L.r);
+  hipError_t e = launch_EH(p->g, p->tb, p->maps, d_y, p->at<c32>(p->L.work), r, p->qpart(), p->adj_groups, st);
+  hipEvent_t stop = nullptr;
+  if (e == hipSuccess && timed_ehe_begin(p, st, &stop) != SENSE_OK) e = hipErrorUnknown;
+  if (e == hipSuccess)
+    e = launch_cg_small(p->g, p->tb, p->maps, r, x, max_iter, lambda, cg, p->at<CgInfo>(p->L.info), d_info, st);
+  if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
+  return e;
+}
+
 static hipError_t enqueue_solve(sense_plan p, const void* d_y, c32* x, int32_t max_iter, float lambda,
                                 const CgArgs& cg, CgInfo* d_info, hipStream_t st) {
+  if (small_solve(p)) return enqueue_small_solve(p, d_y, x, max_iter, lambda, cg, d_info, st);
   hipError_t e = enqueue_solve_begin(p, d_y, x, cg, st);
   for (int k = 0; k < max_iter && e == hipSuccess; ++k) e = enqueue_iteration(p, x, lambda, k, cg, st);
   if (e == hipSuccess) e = enqueue_solve_end(p, x, max_iter, cg, d_info, st);

@@ -115,3 +115,8 @@ hipError_t enqueue_iteration(sense_plan p, sense::c32* x, float lambda, int k, c
                              hipStream_t st);
 hipError_t enqueue_solve_end(sense_plan p, sense::c32* x, int K, const sense::CgArgs& cg, sense::CgInfo* d_info,
                              hipStream_t st);
+// Whether the plan's solves run as one whole-solve launch after E^H y, and
+// that enqueue.
+bool small_solve(const sense_plan_s* p);
+hipError_t enqueue_small_solve(sense_plan p, const void* d_y, sense::c32* x, int32_t max_iter, float lambda,
+                               const sense::CgArgs& cg, sense::CgInfo* d_info, hipStream_t st);

@@ -232,3 +232,66 @@ def test_cg_graph_replay_matches_eager():
         assert torch.equal(out, ref_tol)
         res = plan.cg(yd, 15, out=out)
         assert torch.equal(out, ref)
+
+
+SMALL_CASES = [  # ny, nx, coils, batch, per-slice maps, storage
+    (8, 8, 2, 2, True, "c64"),
+    (16, 40, 3, 1, False, "c64"),
+    (32, 64, 4, 3, True, "c64"),
+    (48, 24, 3, 1, False, "c64"),
+    (64, 64, 8, 2, False, "bf16"),
+    (64, 33, 4, 1, True, "c64"),
+]
+
+
+@pytest.mark.parametrize("ny,nx,nc,b,per,st", SMALL_CASES)
+def test_small_whole_solve_matches_oracle(ny, nx, nc, b, per, st):
+    """Slices of at most 64 x 64 run the whole solve in one workgroup per
+    batch element (every supported length, ragged widths, batches, 16-bit
+    maps): x, the iteration count, the status and the rho history against
+    the oracle's CG on the same (quantised) inputs."""
+    from gpu_common import quantise
+    maps = c64(0.5 * synth.complex_normal((b, nc, ny, nx) if per else (nc, ny, nx), ny + nx))
+    mask = synth.mask_variable_density(ny, 2.0, max(2, ny // 8), seed=ny)
+    xt = c64(synth.complex_normal((b, ny, nx), 7))
+    mq = quantise(maps, st)
+    y = np.concatenate([oracle.E(xt[i:i + 1], mq[i] if per else mq, mask) for i in range(b)])
+    y = c64(y + 1e-3 * synth.complex_normal(y.shape, 8) * mask[None, None, :, None])
+    K = 12
+    xo = np.empty_like(xt)
+    ho = np.empty((b, K + 1))
+    for i in range(b):
+        xo[i:i + 1], _, _, ho[i:i + 1] = oracle.cg(y[i:i + 1], mq[i] if per else mq, mask, K)
+    with sense.Plan(to_dev(maps), mask, batch=b, maps_storage=st) as plan:
+        assert plan.coil_groups()[0] == 1
+        res = plan.cg(to_dev(y), K, history=True)
+    err = rel_l2(to_host(res.x), xo)
+    log(f"small {ny}x{nx} C={nc} B={b} {st}: rel-L2 {err:.3e}")
+    assert err <= TOL_FP32
+    assert list(res.iters) == [K] * b and list(res.status) == [sense.MAXITER] * b
+    assert np.allclose(res.rho_hist.cpu().numpy(), ho, rtol=1e-4)
+    assert np.allclose(res.rho0, ho[:, 0], rtol=1e-5)
+
+
+def test_small_whole_solve_equals_graph_replay_and_engine():
+    """The whole-solve launch replays bitwise from its graph, and a small
+    request in the serving engine (run whole at admission) equals the plain
+    solve bitwise."""
+    w = synth.SMALL_64
+    imgs, maps, mask, y = _problem(w)
+    with sense.Plan(to_dev(maps), mask) as plan, sense.Plan(to_dev(maps), mask) as pe:
+        yd = to_dev(y)
+        plan.set_graphs(False)
+        ref = plan.cg(yd, w.iters).x.clone()
+        plan.set_graphs(True)
+        for _ in range(3):
+            assert torch.equal(plan.cg(yd, w.iters).x, ref)
+        x = torch.empty_like(ref)
+        with sense.Engine(budget_bytes=1 << 30, max_slots=2) as eng:
+            assert eng.admit(pe, yd, x, w.iters) == 0
+            done = []
+            while not done:
+                eng.step()
+                done = eng.poll()
+        torch.cuda.synchronize()
+        assert torch.equal(x, ref)
