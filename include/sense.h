@@ -188,6 +188,10 @@ SENSE_API sense_status sense_apply_EHE(sense_plan plan, const void* d_p, void* d
  *              plan also keeps the last result for sense_plan_cg_info.
  *   d_rho_hist optional device array [B][max_iter + 1] of fp64 rho_k
  *              (entries past the stop iteration are left untouched).
+ * 2D slices of at most 64 columns with Ny in {8, 16, 32, 48, 64} and one
+ * coil group run the whole loop in one launch after E^H y (one workgroup
+ * per batch element, vectors in registers, block reductions); larger
+ * problems run one fused launch per iteration.  Both follow the loop above.
  */
 SENSE_API sense_status sense_cg_solve(sense_plan plan, const void* d_y, void* d_x, int32_t max_iter,
                             double rel_tol, double lambda, sense_cg_info* d_info,
@@ -252,7 +256,8 @@ SENSE_API sense_status sense_plan_profile(sense_plan plan, int64_t* n_launches, 
  * launch) per distinct (ny, maps storage, maps staging) group; each problem
  * uses its own CG state, coil groups and reduction order, so its result is
  * bitwise the same as sense_cg_solve alone.  Requests admitted between steps
- * join at the next step.  poll returns the slots whose solves are complete
+ * join at the next step; a small slice that sense_cg_solve runs in one
+ * launch runs its whole solve at admission instead.  poll returns the slots whose solves are complete
  * (d_x written; sense_plan_cg_info gives the info) and frees them.  The
  * engine owns its streams: admissions and steps are ordered on one of them,
  * and the groups of a step after the first run on side streams forked from
