@@ -198,6 +198,32 @@ SENSE_API sense_status sense_cg_solve(sense_plan plan, const void* d_y, void* d_
                             double* d_rho_hist, void* stream);
 
 /*
+ * The same CG-SENSE solve without a plan, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Every table and work vector of the
+ * solve lives in one static device array of 64 MiB per GPU (held from the
+ * library's load on that GPU until the process ends); the call allocates
+ * nothing and enqueues: a few small table-copy kernels (the tables travel
+ * in kernel arguments), E^H y, the iterations and the final test, on
+ * stream.  Results equal those of sense_cg_solve on a plan with the same
+ * descriptor, maps and mask.
+ *   desc, d_maps, h_mask   as for sense_plan_create (d_maps only borrowed
+ *                          for the call; h_mask read during the call).
+ *   d_y, d_x, max_iter, rel_tol, lambda, d_info, d_rho_hist
+ *                          as for sense_cg_solve.
+ * Limits: ndim = 2, nx a supported length, and the plan workspace
+ * sense_plan_device_bytes(desc) at most 64 MiB; larger problems return
+ * SENSE_ERR_UNSUPPORTED (use a plan).  All calls on one GPU share its
+ * array: calls that overlap on one GPU (other streams, other host threads)
+ * race and must be serialised by the caller.  The array keeps the last
+ * call's contents; each call initialises everything it reads.
+ */
+SENSE_API sense_status sense_cg_solve_static(const sense_desc* desc, const void* d_maps, const uint8_t* h_mask,
+                                             const void* d_y, void* d_x, int32_t max_iter, double rel_tol,
+                                             double lambda, sense_cg_info* d_info, double* d_rho_hist,
+                                             void* stream);
+
+/*
  * Graph replay of whole solves (default on).  The first sense_cg_solve with a
  * given argument set (d_y, d_x, max_iter, rel_tol, lambda, d_info,
  * d_rho_hist) captures every kernel of the solve into a HIP graph on a

@@ -47,7 +47,7 @@ static size_t kspace_bytes(const sense_plan_s* p) {
 
 constexpr long kMinSplitVoxels = 8192;
 
-static Layout make_layout(const sense_desc& d) {
+Layout make_layout(const sense_desc& d) {
   Layout L{};
   const size_t nvox = (size_t)d.nx * d.ny * d.nz;
   const size_t B = (size_t)d.batch, C = (size_t)d.ncoils;
@@ -103,7 +103,7 @@ static Layout make_layout(const sense_desc& d) {
   return L;
 }
 
-static sense_status validate_desc(const sense_desc* d) {
+sense_status validate_desc(const sense_desc* d) {
   if (!d) return fail(SENSE_ERR_INVALID, "desc is NULL");
   if (d->ndim != 2 && d->ndim != 3) return fail(SENSE_ERR_INVALID, "ndim must be 2 or 3");
   if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->ncoils < 1 || d->batch < 1)
@@ -127,7 +127,70 @@ static sense_status validate_desc(const sense_desc* d) {
   return SENSE_OK;
 }
 
+
+void host_twiddles(long n, c32* out) {
+  // exp(-2 pi i e / n) in fp64, rounded once to fp32
+  for (long e2 = 0; e2 < n; ++e2) {
+    const double a = -2.0 * 3.141592653589793238462643383279502884 * (double)e2 / (double)n;
+    out[e2] = c32{(float)std::cos(a), (float)std::sin(a)};
+  }
+}
+
+void host_mask_tables(const uint8_t* h_mask, long ny, long nz, uint8_t* mask, float* mu, int32_t* rows_s,
+                      int32_t* rows_u, int* n_s, int* n_u) {
+  int ns = 0, nu = 0;
+  for (long i = 0; i < ny * nz; ++i) {
+    mask[i] = h_mask[i] ? 1 : 0;
+    if (mask[i]) rows_s[ns++] = (int32_t)i;
+    else rows_u[nu++] = (int32_t)i;
+  }
+  // Uncentred mask of the hybrid normal operator with the 1/ny of the
+  // unnormalised forward/inverse pair folded in.
+  for (long k = 0; k < ny; ++k) mu[k] = mask[(k + ny / 2) % ny] ? (float)(1.0 / (double)ny) : 0.f;
+  *n_s = ns;
+  *n_u = nu;
+}
+
 }  // namespace sense
+
+void init_plan_fields(sense_plan_s* p, const sense_desc& d, const void* d_maps) {
+  p->d = d;
+  p->maps = d_maps;
+  p->full_ops = sense::length_supported(d.nx);
+  p->profiling = false;
+  p->events_used = 0;
+  p->graphs = false;
+  p->busy = false;
+  p->cap_stream = nullptr;
+  p->gexec = nullptr;
+  p->mem = nullptr;
+  p->L = sense::make_layout(d);
+  p->ngroups = p->L.dgroups;
+  p->adj_groups = p->L.agroups;
+  const size_t nvox = (size_t)d.nx * d.ny * d.nz;
+  p->g.nx = d.nx;
+  p->g.ny = d.ny;
+  p->g.nz = d.nz;
+  p->g.ncoils = d.ncoils;
+  p->g.batch = d.batch;
+  p->g.maps_bstride = d.maps_shared ? 0 : (long)(nvox * d.ncoils);
+  p->g.maps_storage = d.maps_storage;
+  p->g.kspace_storage = d.kspace_storage;
+  p->g.kspace_compact = d.kspace_compact;
+}
+
+void bind_tables(sense_plan_s* p) {
+  using namespace sense;
+  p->tb.tw_x = p->at<c32>(p->L.tw_x);
+  p->tb.tw_y = p->at<c32>(p->L.tw_y);
+  p->tb.tw_z = p->at<c32>(p->L.tw_z);
+  p->tb.mu_y = p->at<float>(p->L.mu_y);
+  p->tb.mask_c = p->at<uint8_t>(p->L.mask_c);
+  p->tb.rows_s = p->at<int32_t>(p->L.rows_s);
+  p->tb.n_rows_s = p->n_rows_s;
+  p->tb.rows_u = p->at<int32_t>(p->L.rows_u);
+  p->tb.n_rows_u = p->n_rows_u;
+}
 
 using namespace sense;
 
@@ -219,8 +282,8 @@ hipError_t enqueue_small_solve(sense_plan p, const void* d_y, c32* x, int32_t ma
   return e;
 }
 
-static hipError_t enqueue_solve(sense_plan p, const void* d_y, c32* x, int32_t max_iter, float lambda,
-                                const CgArgs& cg, CgInfo* d_info, hipStream_t st) {
+hipError_t enqueue_solve(sense_plan p, const void* d_y, c32* x, int32_t max_iter, float lambda, const CgArgs& cg,
+                         CgInfo* d_info, hipStream_t st) {
   if (small_solve(p)) return enqueue_small_solve(p, d_y, x, max_iter, lambda, cg, d_info, st);
   hipError_t e = enqueue_solve_begin(p, d_y, x, cg, st);
   for (int k = 0; k < max_iter && e == hipSuccess; ++k) e = enqueue_iteration(p, x, lambda, k, cg, st);
@@ -265,32 +328,12 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
 
     auto* p = new (std::nothrow) sense_plan_s();
     if (!p) return fail(SENSE_ERR_NOMEM, "host allocation failed");
-    p->d = d;
-    p->maps = d_maps;
-    p->full_ops = length_supported(d.nx);
-    p->profiling = false;
-    p->events_used = 0;
+    init_plan_fields(p, d, d_maps);
     p->graphs = true;
-    p->busy = false;
-    p->cap_stream = nullptr;
-    p->gexec = nullptr;
     if (hipGetDevice(&p->device) != hipSuccess) {
       delete p;
       return fail(SENSE_ERR_DEVICE, "hipGetDevice failed");
     }
-    p->L = make_layout(d);
-    p->ngroups = p->L.dgroups;
-    p->adj_groups = p->L.agroups;
-    const size_t nvox = (size_t)d.nx * d.ny * d.nz;
-    p->g.nx = d.nx;
-    p->g.ny = d.ny;
-    p->g.nz = d.nz;
-    p->g.ncoils = d.ncoils;
-    p->g.batch = d.batch;
-    p->g.maps_bstride = d.maps_shared ? 0 : (long)(nvox * d.ncoils);
-    p->g.maps_storage = d.maps_storage;
-    p->g.kspace_storage = d.kspace_storage;
-    p->g.kspace_compact = d.kspace_compact;
 
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&p->mem), p->L.total);
     if (e != hipSuccess) {
@@ -298,30 +341,18 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
       return fail(SENSE_ERR_NOMEM, "hipMalloc of " + std::to_string(p->L.total) + " bytes failed");
     }
 
-    // Host tables: twiddles exp(-2 pi i e / n) in fp64, rounded once to fp32.
-    auto twiddles = [](long n) {
-      std::vector<c32> t((size_t)n);
-      for (long e2 = 0; e2 < n; ++e2) {
-        const double a = -2.0 * 3.141592653589793238462643383279502884 * (double)e2 / (double)n;
-        t[(size_t)e2] = c32{(float)std::cos(a), (float)std::sin(a)};
-      }
-      return t;
-    };
-    std::vector<c32> twx = twiddles(d.nx), twy = twiddles(d.ny), twz = twiddles(d.nz);
+    std::vector<c32> twx((size_t)d.nx), twy((size_t)d.ny), twz((size_t)d.nz);
+    host_twiddles(d.nx, twx.data());
+    host_twiddles(d.ny, twy.data());
+    host_twiddles(d.nz, twz.data());
     const long rows_total = d.ny * d.nz;
     std::vector<uint8_t> mask((size_t)rows_total);
-    std::vector<int32_t> rs, ru;
-    for (long i = 0; i < rows_total; ++i) {
-      mask[(size_t)i] = h_mask[i] ? 1 : 0;
-      (mask[(size_t)i] ? rs : ru).push_back((int32_t)i);
-    }
-    // Uncentred mask of the hybrid normal operator with the 1/ny of the
-    // unnormalised forward/inverse pair folded in.
+    std::vector<int32_t> rs((size_t)rows_total), ru((size_t)rows_total);
     std::vector<float> mu((size_t)d.ny);
-    for (long k = 0; k < d.ny; ++k)
-      mu[(size_t)k] = mask[(size_t)((k + d.ny / 2) % d.ny)] ? (float)(1.0 / (double)d.ny) : 0.f;
-    p->n_rows_s = (int)rs.size();
-    p->n_rows_u = (int)ru.size();
+    host_mask_tables(h_mask, d.ny, d.nz, mask.data(), mu.data(), rs.data(), ru.data(), &p->n_rows_s,
+                     &p->n_rows_u);
+    rs.resize((size_t)p->n_rows_s);
+    ru.resize((size_t)p->n_rows_u);
 
     auto up = [&](size_t off, const void* src, size_t bytes) {
       if (bytes == 0 || e != hipSuccess) return;
@@ -340,15 +371,7 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
       delete p;
       return device_fail(e, "table upload");
     }
-    p->tb.tw_x = p->at<c32>(p->L.tw_x);
-    p->tb.tw_y = p->at<c32>(p->L.tw_y);
-    p->tb.tw_z = p->at<c32>(p->L.tw_z);
-    p->tb.mu_y = p->at<float>(p->L.mu_y);
-    p->tb.mask_c = p->at<uint8_t>(p->L.mask_c);
-    p->tb.rows_s = p->at<int32_t>(p->L.rows_s);
-    p->tb.n_rows_s = p->n_rows_s;
-    p->tb.rows_u = p->at<int32_t>(p->L.rows_u);
-    p->tb.n_rows_u = p->n_rows_u;
+    bind_tables(p);
     *out = p;
     return SENSE_OK;
   } catch (...) {

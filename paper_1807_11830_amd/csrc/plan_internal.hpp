@@ -23,6 +23,15 @@ struct Layout {
 };
 
 sense_status fail(sense_status s, const std::string& msg);
+// Size and format checks of a descriptor; workspace layout of a plan for it.
+sense_status validate_desc(const sense_desc* d);
+Layout make_layout(const sense_desc& d);
+// Host tables: twiddles exp(-2 pi i e / n) (fp64, rounded once to fp32);
+// the 0/1 centred mask [nz][ny], the uncentred mask / ny of the 2D normal
+// operator, and the sampled / unsampled row ids (z * ny + y, increasing).
+void host_twiddles(long n, c32* out);
+void host_mask_tables(const uint8_t* h_mask, long ny, long nz, uint8_t* mask, float* mu, int32_t* rows_s,
+                      int32_t* rows_u, int* n_s, int* n_u);
 sense_status device_fail(hipError_t e, const char* what);
 bool overlap(const void* a, size_t na, const void* b, size_t nb);
 size_t storage_bytes(int st);
@@ -106,6 +115,11 @@ struct sense_plan_s {
   }
 };
 
+// Descriptor-derived fields of a plan (geometry, layout, default coil
+// groups; graphs off, no memory); bind_tables points the table pointers
+// into p->mem once it is set.
+void init_plan_fields(sense_plan_s* p, const sense_desc& d, const void* d_maps);
+void bind_tables(sense_plan_s* p);
 sense_status check_plan(sense_plan p);
 sense_status check_solve_args(sense_plan p, const void* d_y, void* d_x, int32_t max_iter, double rel_tol,
                               double lambda);
@@ -115,6 +129,10 @@ hipError_t enqueue_iteration(sense_plan p, sense::c32* x, float lambda, int k, c
                              hipStream_t st);
 hipError_t enqueue_solve_end(sense_plan p, sense::c32* x, int K, const sense::CgArgs& cg, sense::CgInfo* d_info,
                              hipStream_t st);
+// A whole solve: E^H y, the iterations and the final test (or the one-launch
+// small solve).
+hipError_t enqueue_solve(sense_plan p, const void* d_y, sense::c32* x, int32_t max_iter, float lambda,
+                         const sense::CgArgs& cg, sense::CgInfo* d_info, hipStream_t st);
 // Whether the plan's solves run as one whole-solve launch after E^H y, and
 // that enqueue.
 bool small_solve(const sense_plan_s* p);

@@ -57,7 +57,7 @@ ABI_FUNCTIONS = ("sense_plan_device_bytes", "sense_plan_create", "sense_plan_des
                  "sense_plan_set_graphs", "sense_plan_set_maps", "sense_plan_set_coil_groups",
                  "sense_plan_coil_groups", "sense_engine_create", "sense_engine_destroy",
                  "sense_engine_admit", "sense_engine_step", "sense_engine_poll", "sense_engine_stats",
-                 "sense_engine_sync", "sense_last_error", "sense_version")
+                 "sense_engine_sync", "sense_last_error", "sense_version", "sense_cg_solve_static")
 
 _lib = None
 
@@ -81,6 +81,7 @@ def lib():
     L.sense_apply_EHE.argtypes = [P, P, P, D, P]
     L.sense_apply_rss.argtypes = [P, P, P, P]
     L.sense_cg_solve.argtypes = [P, P, P, I32, D, D, P, P, P]
+    L.sense_cg_solve_static.argtypes = [ctypes.POINTER(Desc), P, P, P, P, I32, D, D, P, P, P]
     L.sense_plan_cg_info.argtypes = [P, P, P]
     L.sense_plan_set_profiling.argtypes = [P, I32]
     L.sense_plan_set_graphs.argtypes = [P, I32]
@@ -374,6 +375,49 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(lib().sense_plan_profile(self._h, ctypes.byref(n), ctypes.byref(ms)))
         return int(n.value), float(ms.value)
+
+
+def cg_solve_static(maps: torch.Tensor, mask, y: torch.Tensor, x: torch.Tensor, max_iter: int,
+                    tol: float = 0.0, lam: float = 0.0, batch: int = 1, maps_storage: str = "c64",
+                    kspace_storage: str = "c64", info: torch.Tensor | None = None,
+                    rho_hist: torch.Tensor | None = None, stream=None) -> None:
+    """CG-SENSE of a 2D problem without a plan (sense_cg_solve_static).
+
+    The library allocates nothing: its tables and work vectors live in a
+    static device array (64 MiB per GPU).  maps [C][Ny][Nx] or
+    [B][C][Ny][Nx] already in ``maps_storage`` (complex64, or interleaved
+    16-bit pairs with a trailing 2), mask uint8 [Ny] centred, y k-space in
+    ``kspace_storage``, x the complex64 [B][Ny][Nx] output; info (optional)
+    a device uint8 tensor of 24 * B bytes receiving sense_cg_info per
+    problem, rho_hist (optional) float64 [B][max_iter + 1].  Calls on one
+    GPU must not overlap."""
+    packed = maps.dtype in (torch.bfloat16, torch.float16)
+    mdim = maps.dim() - (1 if packed else 0)
+    if mdim == 3:
+        shared, (ncoils, ny, nx) = 1, tuple(maps.shape[:3])
+    elif mdim == 4:
+        shared, (ncoils, ny, nx) = 0, tuple(maps.shape[1:4])
+    else:
+        raise SenseError(1, "maps must be [C][Ny][Nx] or [B][C][Ny][Nx]")
+    m = np.ascontiguousarray(np.asarray(mask), dtype=np.uint8)
+    if m.size != ny:
+        raise SenseError(1, f"mask needs {ny} entries")
+    for t, name in ((maps, "maps"), (y, "y"), (x, "x")):
+        if not t.is_cuda or not t.is_contiguous():
+            raise SenseError(1, f"{name} must be a contiguous GPU tensor")
+    if x.dtype != torch.complex64 or x.numel() != batch * ny * nx:
+        raise SenseError(1, "x must be complex64 [B][Ny][Nx]")
+    if info is not None and (info.dtype != torch.uint8 or info.numel() != 24 * batch or not info.is_cuda):
+        raise SenseError(1, "info must be a device uint8 tensor of 24 * batch bytes")
+    if rho_hist is not None and (rho_hist.dtype != torch.float64 or rho_hist.numel() != batch * (max_iter + 1)):
+        raise SenseError(1, "rho_hist must be float64 [B][max_iter + 1]")
+    d = Desc(2, int(nx), int(ny), 1, int(ncoils), int(batch), STORAGE[maps_storage], STORAGE[kspace_storage],
+             shared, 0)
+    with torch.cuda.device(x.device):
+        _check(lib().sense_cg_solve_static(ctypes.byref(d), _ptr(maps), m.ctypes.data_as(ctypes.c_void_p),
+                                           _ptr(y), _ptr(x), int(max_iter), float(tol), float(lam),
+                                           _ptr(info) if info is not None else None,
+                                           _ptr(rho_hist) if rho_hist is not None else None, _stream(stream)))
 
 
 class Engine:
