@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--no-context", action="store_true",
                     help="skip the context figures (copy peak, torch.fft E^H E, serving summary)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving summary only (profiling runs)")
     return ap.parse_args()
 
 
@@ -699,7 +701,7 @@ def run_cgsense(args):
     plan.close()
     del maps, imgs, y, x, p, q
     torch.cuda.empty_cache()
-    if not args.no_context:
+    if not (args.no_context or args.no_serving):
         out["serving"] = serving_summary()
     print(json.dumps(out), flush=True)
 
