@@ -62,7 +62,28 @@ constexpr bool ehe_stage_maps() {
   }
 }
 
-template <int N, int ST, bool CG, bool SM>
+// Cache policy of the fused kernel's accesses (STREAM = streaming launch):
+// streamed where one block's row segment (TX values) covers whole 128-byte
+// lines, default otherwise.  Streaming pays only when a launch's data is
+// far larger than the caches and read once (160 slices of 256^2 with 12
+// coils: 1.66 GB per launch, 357.7 -> 340.5 us); problems that stay in L2
+// and the memory-side cache between launches lose their hits (one 256^2
+// slice with 16 coils: 26.2 -> 28.0 us; 16 slices of 320^2 with 32 coils,
+// 0.52 GB: 238 -> 240 us).  Plan launches stream from kStreamBytes of
+// algorithmic traffic on; batched serving launches never do.  Lengths
+// below 128 points are never part of such a launch's shape here, so only
+// 128 points and up have streaming instantiations.
+constexpr double kStreamBytes = 1024.0 * 1024.0 * 1024.0;
+template <int N, int SB>
+constexpr int ehe_cache_policy() {
+  return EheLen<N>::TX * SB >= 128 ? kCacheStream : kCacheDefault;
+}
+template <int N>
+constexpr bool ehe_has_stream() {
+  return N >= 128;
+}
+
+template <int N, int ST, bool CG, bool SM, bool STREAM>
 __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, const int b, const int grp) {
   constexpr int T = EheLen<N>::T;
   constexpr int E = EheLen<N>::E;
@@ -71,6 +92,8 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   using Rad = typename EheLen<N>::R;
   using SType = typename StorageT<ST>::T;
   constexpr int SB = (int)sizeof(SType);
+  constexpr int CPS = STREAM ? ehe_cache_policy<N, SB>() : kCacheDefault;                 // maps
+  constexpr int CPV = STREAM ? ehe_cache_policy<N, (int)sizeof(c32)>() : kCacheDefault;  // image vectors
 
   // one LDS exchange buffer (each stage boundary waits for its readers)
   __shared__ c32 xbuf[N * TX];
@@ -157,7 +180,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     const Buf bp = make_buf(P.p_in + (long)b * nvox, img_bytes);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      p[j] = buf_load_c64(bp, voff * 8u, (uint32_t)j * rstep * 8u);
+      p[j] = buf_load_c64<CPV>(bp, voff * 8u, (uint32_t)j * rstep * 8u);
       q[j] = {0.f, 0.f};
     }
   } else {
@@ -189,10 +212,10 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
       sfor<G>([&](auto jc) {
         constexpr int i = decltype(jc)::value;
         const uint32_t so = (uint32_t)(g0 + i) * rstep * 8u;
-        lp[slot][i] = buf_load_c64(bp, lo, so);
-        lr[slot][i] = buf_load_c64(br, lo, so);
-        lq[slot][i] = buf_load_c64(bq, lo, so);
-        lx[slot][i] = buf_load_c64(bx, lox, so);  // unconditional: keeps the waits exact
+        lp[slot][i] = buf_load_c64<CPV>(bp, lo, so);
+        lr[slot][i] = buf_load_c64<CPV>(br, lo, so);
+        lq[slot][i] = buf_load_c64<CPV>(bq, lo, so);
+        lx[slot][i] = buf_load_c64<CPV>(bx, lox, so);  // unconditional: keeps the waits exact
       });
     };
     auto update_group = [&](auto gc, int slot) {
@@ -206,9 +229,9 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
         const c32 rv = {(float)((double)lr[slot][i].re - a * qv.re), (float)((double)lr[slot][i].im - a * qv.im)};
         const c32 pv = {(float)((double)rv.re + bt * pv0.re), (float)((double)rv.im + bt * pv0.im)};
         if (valid && owner) {
-          buf_store_c64(bx, xv, lo, so);
-          buf_store_c64(bro, rv, lo, so);
-          buf_store_c64(bpo, pv, lo, so);
+          buf_store_c64<CPV>(bx, xv, lo, so);
+          buf_store_c64<CPV>(bro, rv, lo, so);
+          buf_store_c64<CPV>(bpo, pv, lo, so);
         }
         p[j] = pv;
         if (valid) rho_acc += (double)rv.re * (double)rv.re + (double)rv.im * (double)rv.im;
@@ -235,7 +258,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   auto load_s = [&](c32* s, int c) {
     const Buf bs = make_buf(S + (long)c * nvox, coil_bytes);
 #pragma unroll
-    for (int j = 0; j < E; ++j) s[j] = buf_load_st<ST>(bs, voff, (uint32_t)j * rstep);
+    for (int j = 0; j < E; ++j) s[j] = buf_load_st<ST, CPS>(bs, voff, (uint32_t)j * rstep);
   };
   // One coil: u = S p, forward transform, mask, inverse transform,
   // q += conj(S) u.
@@ -275,7 +298,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     const Buf bg = make_buf(P.qpart + (long)grp * P.qpart_gstride + (long)b * nvox, img_bytes);
     if (valid) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) buf_store_c64(bg, q[j], voff * 8u, (uint32_t)j * rstep * 8u);
+      for (int j = 0; j < E; ++j) buf_store_c64<CPV>(bg, q[j], voff * 8u, (uint32_t)j * rstep * 8u);
     }
     if constexpr (CG) {
       // group 0 leaves <r,r> of the residual it stored in the prologue
@@ -293,7 +316,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     for (int j = 0; j < E; ++j) {
       c32 qq = {q[j].re + P.lambda * p[j].re, q[j].im + P.lambda * p[j].im};
       if (valid) {
-        buf_store_c64(bq, qq, voff * 8u, (uint32_t)j * rstep * 8u);
+        buf_store_c64<CPV>(bq, qq, voff * 8u, (uint32_t)j * rstep * 8u);
         eta += (double)p[j].re * (double)qq.re + (double)p[j].im * (double)qq.im;
       }
     }
@@ -309,7 +332,7 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
     for (int j = 0; j < E; ++j) {
       c32 qq = {q[j].re + P.lambda * p[j].re, q[j].im + P.lambda * p[j].im};
       if (valid) {
-        buf_store_c64(bq, qq, voff * 8u, (uint32_t)j * rstep * 8u);
+        buf_store_c64<CPV>(bq, qq, voff * 8u, (uint32_t)j * rstep * 8u);
         acc[0] += (double)p[j].re * (double)qq.re + (double)p[j].im * (double)qq.im;
         acc[1] += (double)qq.re * (double)qq.re + (double)qq.im * (double)qq.im;
       }
@@ -324,10 +347,10 @@ __device__ __forceinline__ void ehe2d_body(const EheParams& P, const int tile, c
   }
 }
 
-template <int N, int ST, bool CG, bool SM>
+template <int N, int ST, bool CG, bool SM, bool STREAM>
 __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX) ehe2d_kernel(EheParams P) {
   const BlockId id = xcd_block();
-  ehe2d_body<N, ST, CG, SM>(P, (int)id.x, (int)id.y, (int)id.z);
+  ehe2d_body<N, ST, CG, SM, STREAM>(P, (int)id.x, (int)id.y, (int)id.z);
 }
 
 // Batched CG launch over many independent single-slice problems of the same
@@ -339,7 +362,7 @@ __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX)
     ehe2d_table_kernel(const EheParams* __restrict__ table) {
   const EheParams P = table[blockIdx.y];
   if ((long)blockIdx.x >= (long)P.ntiles || (int)blockIdx.z >= P.ngroups) return;
-  ehe2d_body<N, ST, true, SM>(P, blockIdx.x, 0, blockIdx.z);
+  ehe2d_body<N, ST, true, SM, false>(P, blockIdx.x, 0, blockIdx.z);
 }
 
 // The same with the table passed by value in the kernel arguments.
@@ -347,7 +370,7 @@ template <int N, int ST, bool SM>
 __global__ void __launch_bounds__(EheLen<N>::T * EheLen<N>::TX) ehe2d_inline_kernel(EheInline table) {
   const EheParams& P = table.p[blockIdx.y];
   if ((long)blockIdx.x >= (long)P.ntiles || (int)blockIdx.z >= P.ngroups) return;
-  ehe2d_body<N, ST, true, SM>(P, blockIdx.x, 0, blockIdx.z);
+  ehe2d_body<N, ST, true, SM, false>(P, blockIdx.x, 0, blockIdx.z);
 }
 
 int ehe_tile_width(long ny) {
@@ -399,15 +422,35 @@ bool ehe_staged(long ny, int maps_storage, long nx, const void* maps) {
   return can && (nx * sb) % 16 == 0 && reinterpret_cast<uintptr_t>(maps) % 16 == 0;
 }
 
-template <int N, int ST, bool CG>
-static void launch_ehe_kernel(const Geom& g, const EheParams& P, dim3 grid, dim3 block, hipStream_t st) {
+template <int N, int ST, bool CG, bool STREAM>
+static void launch_ehe_kernel_nt(const Geom& g, const EheParams& P, dim3 grid, dim3 block, hipStream_t st) {
   if constexpr (ehe_stage_maps<N, ST>()) {
     if (ehe_staged(N, ST, g.nx, P.maps)) {
-      hipLaunchKernelGGL((ehe2d_kernel<N, ST, CG, true>), grid, block, 0, st, P);
+      hipLaunchKernelGGL((ehe2d_kernel<N, ST, CG, true, STREAM>), grid, block, 0, st, P);
       return;
     }
   }
-  hipLaunchKernelGGL((ehe2d_kernel<N, ST, CG, false>), grid, block, 0, st, P);
+  hipLaunchKernelGGL((ehe2d_kernel<N, ST, CG, false, STREAM>), grid, block, 0, st, P);
+}
+
+// Whether a plan launch of this shape streams its accesses (see
+// ehe_cache_policy): algorithmic bytes of one fused launch, maps in their
+// storage plus eight image vectors per slice.
+static bool ehe_stream(const Geom& g) {
+  const double sb = g.maps_storage == ST_C64 ? 8.0 : 4.0;
+  const double bytes = (double)g.batch * (double)(g.nx * g.ny) * (g.ncoils * sb + 64.0);
+  return bytes >= kStreamBytes;
+}
+
+template <int N, int ST, bool CG>
+static void launch_ehe_kernel(const Geom& g, const EheParams& P, dim3 grid, dim3 block, hipStream_t st) {
+  if constexpr (ehe_has_stream<N>()) {
+    if (ehe_stream(g)) {
+      launch_ehe_kernel_nt<N, ST, CG, true>(g, P, grid, block, st);
+      return;
+    }
+  }
+  launch_ehe_kernel_nt<N, ST, CG, false>(g, P, grid, block, st);
 }
 
 template <int N, int ST>
