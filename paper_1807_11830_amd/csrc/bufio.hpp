@@ -34,6 +34,14 @@ struct Buf {
 // read (384 points, 8 columns: 714 -> 867 us).
 constexpr int kCacheDefault = 0;
 constexpr int kCacheStream = 2;
+// Algorithmic traffic from which a plan launch streams (the kernels choose
+// per access whether a streamed line is whole).
+constexpr double kStreamBytes = 1024.0 * 1024.0 * 1024.0;
+// Policy of an access whose block row segment is seg_bytes long.
+template <bool STREAM, int SEG_BYTES>
+constexpr int stream_policy() {
+  return STREAM && SEG_BYTES >= 128 ? kCacheStream : kCacheDefault;
+}
 
 __device__ __forceinline__ Buf make_buf(const void* base, uint32_t bytes) {
   return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3)};

@@ -147,13 +147,20 @@ constexpr int pass_tile() {
   return (AXIS == 2 && T * 32 <= 256) ? 32 : col_tile<T>();
 }
 
-template <int N, int AXIS, int MODE, int ST>
+// STREAM: the launch's data is read or written once and far exceeds the
+// caches, so whole-line accesses take the streaming policy (bufio.hpp); the
+// image X of the forward coil pass is read once per coil and keeps the
+// default policy.
+template <int N, int AXIS, int MODE, int ST, bool STREAM>
 __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) colpass_kernel(ColPass P) {
   constexpr int T = Len<N>::T;
   constexpr int E = Len<N>::E;
   constexpr int TX = pass_tile<T, AXIS>();
   constexpr int NT = T * TX;
   using Rad = typename Len<N>::R;
+  using SType0 = typename StorageT<ST>::T;
+  constexpr int CPW = stream_policy<STREAM, TX * 8>();                      // complex64 data
+  constexpr int CPS = stream_policy<STREAM, TX * (int)sizeof(SType0)>();  // maps
   __shared__ c32 buf[N * TX];
   __shared__ c32 tw[N];
   __shared__ uint8_t msk[N];  // the mask along this pass's line
@@ -198,7 +205,7 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const uint32_t o = voff + (uint32_t)j * rstep;
-        u[j] = cscale(cmul(buf_load_st<ST>(bs, o, 0), buf_load_c64(bx, o * 8u, 0)), sgn);
+        u[j] = cscale(cmul(buf_load_st<ST, CPS>(bs, o, 0), buf_load_c64(bx, o * 8u, 0)), sgn);
       }
     } else {
       const Buf bw = make_buf(P.src + bc * nvox, vbytes);
@@ -209,7 +216,7 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
         // would serialise the loads
         const bool on = MODE == CM_ADJ && P.mask_load ? mask_at(t + T * j) : true;
         const uint32_t o = on ? (voff + (uint32_t)j * rstep) * 8u : kBufOOB;
-        u[j] = cscale(buf_load_c64(bw, o, 0), sgn);
+        u[j] = cscale(buf_load_c64<CPW>(bw, o, 0), sgn);
       }
     }
     if constexpr (MODE == CM_ADJ) {
@@ -231,7 +238,7 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const bool on = (MODE == CM_FWD_COIL || MODE == CM_FWD) && P.mask_store ? mask_at(t + T * j) : true;
-        if (on) buf_store_c64(bd, cscale(u[j], sc), (voff + (uint32_t)j * rstep) * 8u, 0);
+        if (on) buf_store_c64<CPW>(bd, cscale(u[j], sc), (voff + (uint32_t)j * rstep) * 8u, 0);
       }
     }
   } else {
@@ -251,14 +258,14 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
       for (int j = 0; j < E; ++j) {
         const bool on = P.mask_load ? mask_at(t + T * j) : true;
         const uint32_t o = on ? (voff + (uint32_t)j * rstep) * 8u : kBufOOB;
-        u[j] = cscale(buf_load_c64(bw, o, 0), sgn);
+        u[j] = cscale(buf_load_c64<CPW>(bw, o, 0), sgn);
       }
       // the coil's maps are loaded before the transform so their latency
       // hides behind it (measured 16% faster for 256^2 x 12 coils x 160
       // slices than loading them after it, at one wave less per SIMD)
       c32 sv[E];
 #pragma unroll
-      for (int j = 0; j < E; ++j) sv[j] = buf_load_st<ST>(bs, voff + (uint32_t)j * rstep, 0);
+      for (int j = 0; j < E; ++j) sv[j] = buf_load_st<ST, CPS>(bs, voff + (uint32_t)j * rstep, 0);
       fft_line<N, T, +1>(u, t, twt, lv, Rad{});
 #pragma unroll
       for (int j = 0; j < E; ++j) acc[j] = cfma_conj(acc[j], sv[j], cscale(u[j], sgn));
@@ -268,7 +275,7 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
       if (valid) {
         const Buf bg = make_buf(static_cast<c32*>(P.part) + grp * P.part_gstride + b * nvox, vbytes);
 #pragma unroll
-        for (int j = 0; j < E; ++j) buf_store_c64(bg, cscale(acc[j], P.scale), (voff + (uint32_t)j * rstep) * 8u, 0);
+        for (int j = 0; j < E; ++j) buf_store_c64<CPW>(bg, cscale(acc[j], P.scale), (voff + (uint32_t)j * rstep) * 8u, 0);
       }
       return;
     }
@@ -279,14 +286,14 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
     const Buf bp = make_buf(P.addp ? P.addp + b * nvox : P.dst, vbytes);
     c32 pv[E];
 #pragma unroll
-    for (int j = 0; j < E; ++j) pv[j] = buf_load_c64(bp, P.addp ? (voff + (uint32_t)j * rstep) * 8u : kBufOOB, 0);
+    for (int j = 0; j < E; ++j) pv[j] = buf_load_c64<CPW>(bp, P.addp ? (voff + (uint32_t)j * rstep) * 8u : kBufOOB, 0);
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const uint32_t o = (voff + (uint32_t)j * rstep) * 8u;
       c32 qq = cscale(acc[j], P.scale);
       qq = {qq.re + P.lambda * pv[j].re, qq.im + P.lambda * pv[j].im};
       eta += (double)pv[j].re * (double)qq.re + (double)pv[j].im * (double)qq.im;
-      if (valid) buf_store_c64(bd, qq, o, 0);
+      if (valid) buf_store_c64<CPW>(bd, qq, o, 0);
     }
     if (P.eta_part) {
       if (!valid) eta = 0.0;
@@ -438,13 +445,25 @@ static hipError_t launch_colpass(const Geom& g, ColPass P, long n, hipStream_t s
                                           : (long)g.batch * g.ncoils;
     dim3 grid((unsigned)((g.nx + TX - 1) / TX), (unsigned)planes, (unsigned)zdim);
     dim3 block(Len<N>::T * TX);
-    switch (g.maps_storage) {
-      case ST_C64: hipLaunchKernelGGL((colpass_kernel<N, AXIS, MODE, ST_C64>), grid, block, 0, st, P); break;
-      case ST_BF16: hipLaunchKernelGGL((colpass_kernel<N, AXIS, MODE, ST_BF16>), grid, block, 0, st, P); break;
-      case ST_FP16: hipLaunchKernelGGL((colpass_kernel<N, AXIS, MODE, ST_FP16>), grid, block, 0, st, P); break;
-      default: return;
-    }
-    err = hipGetLastError();
+    // every mode reads or writes about two complex64 values per coil voxel;
+    // streaming instantiations exist from 128 points on
+    const bool stream = N >= 128 && (double)g.batch * g.ncoils * (double)(g.nx * g.ny * g.nz) * 16.0 >= kStreamBytes;
+    auto go = [&](auto stc) {
+      constexpr bool S = decltype(stc)::value;
+      if constexpr (S && N < 128) {
+        return;
+      } else {
+        switch (g.maps_storage) {
+          case ST_C64: hipLaunchKernelGGL((colpass_kernel<N, AXIS, MODE, ST_C64, S>), grid, block, 0, st, P); break;
+          case ST_BF16: hipLaunchKernelGGL((colpass_kernel<N, AXIS, MODE, ST_BF16, S>), grid, block, 0, st, P); break;
+          case ST_FP16: hipLaunchKernelGGL((colpass_kernel<N, AXIS, MODE, ST_FP16, S>), grid, block, 0, st, P); break;
+          default: return;
+        }
+        err = hipGetLastError();
+      }
+    };
+    if (stream) go(std::true_type{});
+    else go(std::false_type{});
   });
   return err;
 }

@@ -73,7 +73,6 @@ constexpr bool ehe_stage_maps() {
 // algorithmic traffic on; batched serving launches never do.  Lengths
 // below 128 points are never part of such a launch's shape here, so only
 // 128 points and up have streaming instantiations.
-constexpr double kStreamBytes = 1024.0 * 1024.0 * 1024.0;
 template <int N, int SB>
 constexpr int ehe_cache_policy() {
   return EheLen<N>::TX * SB >= 128 ? kCacheStream : kCacheDefault;
