@@ -276,20 +276,24 @@ SENSE_API sense_status sense_plan_profile(sense_plan plan, int64_t* n_launches, 
  * k-space d_y and output image d_x.  Admission needs a free slot and
  * footprint_bytes (what the caller counts for this request: plan plus its
  * buffers) within the remaining budget; otherwise it returns
- * SENSE_ERR_STATE and the caller retries after poll has freed slots.  A step
- * advances every running slot by one CG iteration with one batched launch of
- * the fused iteration (and, where a problem splits its coils, one combine
- * launch) per distinct (ny, maps storage, maps staging) group; each problem
+ * SENSE_ERR_STATE and the caller retries after poll has freed slots.  The
+ * running slots form groups by (ny, maps storage, maps staging); a step
+ * advances the slots of every group that is not already two steps ahead by
+ * one CG iteration with one batched launch of the fused iteration (and,
+ * where a problem splits its coils, one combine launch) per group, and
+ * returns (when every group is two steps ahead it first waits until one is
+ * not).  Each group runs on a stream (lane) of its own, so groups of small
+ * slices are not held to the pace of groups of large ones.  Each problem
  * uses its own CG state, coil groups and reduction order, so its result is
  * bitwise the same as sense_cg_solve alone.  Requests admitted between steps
- * join at the next step; a small slice that sense_cg_solve runs in one
- * launch runs its whole solve at admission instead.  poll returns the slots whose solves are complete
- * (d_x written; sense_plan_cg_info gives the info) and frees them.  The
- * engine owns its streams: admissions and steps are ordered on one of them,
- * and the groups of a step after the first run on side streams forked from
- * and joined back into it (sense_engine_sync waits for all).  A plan in a
- * slot must not be used or destroyed until its slot is polled.  All calls
- * come from one host thread.
+ * join at their group's next step; a small slice that sense_cg_solve runs in
+ * one launch runs its whole solve at admission instead.  poll returns the
+ * slots whose solves are complete (d_x written; sense_plan_cg_info gives the
+ * info) and frees them.  The engine owns its streams: admissions run on its
+ * own stream, and a lane waits for the latest admission before the first
+ * step of a newly joined slot (sense_engine_sync waits for all streams).  A
+ * plan in a slot must not be used or destroyed until its slot is polled.
+ * All calls come from one host thread.
  */
 typedef struct sense_engine_s* sense_engine;
 

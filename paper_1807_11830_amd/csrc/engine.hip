@@ -3,22 +3,28 @@
 // A slot table holds the solves in flight.  Each admitted request is one
 // single-slice problem with its own plan (maps, mask, workspace, CG state),
 // k-space and output image; admission checks a free slot and a device-memory
-// budget.  A step advances every running slot by one CG iteration with one
-// batched launch of the fused iteration (previous updates + normal operator)
-// per distinct (ny, maps storage) group, followed by one combine launch
-// when a problem of the group splits its coils: block row i of a batched
-// launch runs problem i of the group's device table with its plan's own
-// coil groups, so a problem computes exactly what its own launch would
-// (results are bitwise the same alone or in any mix).  Requests admitted between steps start on the next step; finished
-// slots are reported by poll and freed.  Everything is enqueued on the
-// engine's stream, except that the groups of one step after the first run
-// on up to kLanes side streams forked from and joined back into it (the
-// groups touch disjoint problems); the host never waits for the device
-// except in poll's event queries and the reuse of a table staging buffer.
+// budget.  Running slots are grouped by (ny, maps storage, maps staging); a
+// step gives every group one batched launch of the fused iteration
+// (previous updates + normal operator), followed by one combine launch when a
+// problem of the group splits its coils: block row i of a batched launch runs
+// problem i of the group's table with its plan's own coil groups, so a
+// problem computes exactly what its own launch would (results are bitwise
+// the same alone or in any mix).
+//
+// Groups advance independently: each group keeps its own lane (stream) and
+// its own bound of kAhead enqueued steps, so a group of small slices is not
+// held to the pace of a group of large ones.  A step enqueues one iteration
+// for every group whose lane has room and returns; when no lane has room it
+// first waits for the lane whose oldest step completes first.  Admissions
+// (E^H y and the CG start, or a small slice's whole solve) run on the
+// engine's own stream, and a lane waits for the latest admission before the
+// first step of a newly joined slot.  The host never waits for the device
+// except there, in poll's event queries and in sync.
 #include <algorithm>
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -40,6 +46,7 @@ struct Slot {
   double tol = 0.0;
   float lambda = 0.f;
   size_t footprint = 0;
+  long admit_no = 0;  // engine admission count at this slot's admission
   hipEvent_t done = nullptr;
 };
 
@@ -47,54 +54,56 @@ struct Slot {
 
 struct sense_engine_s {
   int device = -1;
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr;  // admissions
   size_t budget = 0;
   size_t used = 0;
   std::vector<Slot> slots;
-  // batched-launch table: device copy and two pinned staging buffers
-  EheParams* d_ehe = nullptr;
-  EheParams* h_ehe[2] = {nullptr, nullptr};
-  hipEvent_t staged[2] = {nullptr, nullptr};
-  int buf = 0;
   long steps = 0;
-  // the host runs at most kAhead steps ahead of the device, so a request
-  // admitted now starts behind at most kAhead queued steps
-  // (measured: 2 and 4 give the same latencies; without a bound the queue
-  // behind a new request grows with the load)
+  // one lane per group key (up to kLanes keys at a time; more keys share
+  // lanes round-robin): a stream, a ring of the events of its last kAhead
+  // steps, and its own table buffers for groups larger than a
+  // kernel-argument table (device copy, two pinned staging buffers used by
+  // alternate steps)
+  // (measured with one shared bound: 2 and 4 steps ahead give the same
+  // latencies; without a bound the queue behind a new request grows with
+  // the load)
   static constexpr int kAhead = 2;
-  hipEvent_t stepped[kAhead] = {};
-  // side streams for the second and later groups of a step (default
-  // priority, like the engine's stream)
-  static constexpr int kLanes = 3;
-  hipStream_t lane[kLanes] = {};
-  hipEvent_t fork = nullptr;
-  hipEvent_t joined[kLanes] = {};
+  static constexpr int kLanes = 4;
+  struct Lane {
+    hipStream_t st = nullptr;
+    hipEvent_t ev[kAhead] = {};
+    long steps = 0;       // steps enqueued on this lane
+    long admits_seen = 0; // admissions this lane has waited for
+    EheParams* d_ehe = nullptr;
+    EheParams* h_ehe[kAhead] = {};
+  } lane[kLanes];
+  std::map<std::tuple<long, int, bool>, int> lane_of;
+  int next_lane = 0;
   // recorded on the caller's stream at admission: the engine's stream
   // waits for it, so k-space produced there just before is complete
   hipEvent_t admitted = nullptr;
+  // recorded on the engine's stream after every admission; lanes wait for
+  // it before a newly joined slot's first step
+  hipEvent_t admit_mark = nullptr;
+  long admits = 0;
 };
 
 static void engine_free(sense_engine e) {
   if (!e) return;
   if (e->st) (void)hipStreamSynchronize(e->st);
+  for (auto& ln : e->lane) {
+    if (ln.st) (void)hipStreamSynchronize(ln.st);
+    for (auto& ev : ln.ev)
+      if (ev) (void)hipEventDestroy(ev);
+    for (auto& h : ln.h_ehe)
+      if (h) (void)hipHostFree(h);
+    if (ln.d_ehe) (void)hipFree(ln.d_ehe);
+    if (ln.st) (void)hipStreamDestroy(ln.st);
+  }
   for (auto& s : e->slots)
     if (s.done) (void)hipEventDestroy(s.done);
-  for (int i = 0; i < 2; ++i) {
-    if (e->h_ehe[i]) (void)hipHostFree(e->h_ehe[i]);
-    if (e->staged[i]) (void)hipEventDestroy(e->staged[i]);
-  }
-  for (auto& ev : e->stepped)
-    if (ev) (void)hipEventDestroy(ev);
-  for (int i = 0; i < sense_engine_s::kLanes; ++i) {
-    if (e->lane[i]) {
-      (void)hipStreamSynchronize(e->lane[i]);
-      (void)hipStreamDestroy(e->lane[i]);
-    }
-    if (e->joined[i]) (void)hipEventDestroy(e->joined[i]);
-  }
-  if (e->fork) (void)hipEventDestroy(e->fork);
   if (e->admitted) (void)hipEventDestroy(e->admitted);
-  if (e->d_ehe) (void)hipFree(e->d_ehe);
+  if (e->admit_mark) (void)hipEventDestroy(e->admit_mark);
   if (e->st) (void)hipStreamDestroy(e->st);
   delete e;
 }
@@ -111,19 +120,18 @@ sense_status sense_engine_create(size_t budget_bytes, int32_t max_slots, sense_e
   e->slots.resize((size_t)max_slots);
   hipError_t err = hipGetDevice(&e->device);
   if (err == hipSuccess) err = hipStreamCreateWithFlags(&e->st, hipStreamNonBlocking);
-  if (err == hipSuccess) err = hipMalloc(reinterpret_cast<void**>(&e->d_ehe), sizeof(EheParams) * max_slots);
-  for (int i = 0; i < 2 && err == hipSuccess; ++i) {
-    err = hipHostMalloc(reinterpret_cast<void**>(&e->h_ehe[i]), sizeof(EheParams) * max_slots, hipHostMallocDefault);
-    if (err == hipSuccess) err = hipEventCreateWithFlags(&e->staged[i], hipEventDisableTiming);
+  for (auto& ln : e->lane) {
+    // default priority, like the engine's stream
+    if (err == hipSuccess) err = hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking);
+    for (auto& ev : ln.ev)
+      if (err == hipSuccess) err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (err == hipSuccess) err = hipMalloc(reinterpret_cast<void**>(&ln.d_ehe), sizeof(EheParams) * max_slots);
+    for (auto& h : ln.h_ehe)
+      if (err == hipSuccess)
+        err = hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(EheParams) * max_slots, hipHostMallocDefault);
   }
-  for (auto& ev : e->stepped)
-    if (err == hipSuccess) err = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-  for (int i = 0; i < sense_engine_s::kLanes && err == hipSuccess; ++i) {
-    err = hipStreamCreateWithFlags(&e->lane[i], hipStreamNonBlocking);
-    if (err == hipSuccess) err = hipEventCreateWithFlags(&e->joined[i], hipEventDisableTiming);
-  }
-  if (err == hipSuccess) err = hipEventCreateWithFlags(&e->fork, hipEventDisableTiming);
   if (err == hipSuccess) err = hipEventCreateWithFlags(&e->admitted, hipEventDisableTiming);
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&e->admit_mark, hipEventDisableTiming);
   for (auto& s : e->slots)
     if (err == hipSuccess) err = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
   if (err != hipSuccess) {
@@ -186,7 +194,9 @@ sense_status sense_engine_admit(sense_engine e, sense_plan plan, const void* d_y
       if (err == hipSuccess) err = hipEventRecord(sl.done, e->st);
     }
   }
+  if (err == hipSuccess) err = hipEventRecord(e->admit_mark, e->st);
   if (err != hipSuccess) return device_fail(err, "sense_engine_admit");
+  sl.admit_no = ++e->admits;
   sl.used = true;
   sl.finishing = whole || max_iter == 0;
   sl.plan = plan;
@@ -203,6 +213,17 @@ sense_status sense_engine_admit(sense_engine e, sense_plan plan, const void* d_y
   return SENSE_OK;
 }
 
+// Lane of a group key: a lane of its own while fewer than kLanes keys
+// have been seen, then shared round-robin.
+static int lane_for(sense_engine e, const std::tuple<long, int, bool>& key) {
+  auto it = e->lane_of.find(key);
+  if (it != e->lane_of.end()) return it->second;
+  const int l = e->next_lane;
+  e->next_lane = (e->next_lane + 1) % sense_engine_s::kLanes;
+  e->lane_of.emplace(key, l);
+  return l;
+}
+
 sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
   if (!e) return fail(SENSE_ERR_INVALID, "engine is NULL");
   int dev = -1;
@@ -211,7 +232,8 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
   // group the running slots by (ny, maps storage, maps staging): one
   // batched launch each, running the code path each problem's own launch
   // would take
-  std::map<std::tuple<long, int, bool>, std::vector<int>> groups;
+  using Key = std::tuple<long, int, bool>;
+  std::map<Key, std::vector<int>> groups;
   for (size_t i = 0; i < e->slots.size(); ++i) {
     const Slot& sl = e->slots[i];
     if (sl.used && !sl.finishing) {
@@ -224,83 +246,94 @@ sense_status sense_engine_step(sense_engine e, int32_t* n_running) {
   if (n_running) *n_running = running;
   if (running == 0) return SENSE_OK;
 
-  hipError_t err = hipEventSynchronize(e->stepped[e->steps % sense_engine_s::kAhead]);
+  constexpr int A = sense_engine_s::kAhead;
+  // a lane has room when its step kAhead back has completed
+  auto has_room = [&](int l) {
+    const auto& ln = e->lane[l];
+    if (ln.steps < A) return true;
+    return hipEventQuery(ln.ev[ln.steps % A]) == hipSuccess;
+  };
+  // the groups of each lane, in key order
+  std::vector<std::vector<const std::pair<const Key, std::vector<int>>*>> by_lane(sense_engine_s::kLanes);
+  for (auto& g : groups) by_lane[(size_t)lane_for(e, g.first)].push_back(&g);
+  hipError_t err = hipSuccess;
+  bool any = false;
+  for (int l = 0; l < sense_engine_s::kLanes; ++l)
+    if (!by_lane[(size_t)l].empty() && has_room(l)) any = true;
+  // every busy lane is kAhead steps ahead: wait until the first of them has
+  // room (polling their oldest steps' events; the lanes finish in an order
+  // the host cannot know)
+  while (!any && err == hipSuccess) {
+    for (int l = 0; l < sense_engine_s::kLanes; ++l) {
+      if (by_lane[(size_t)l].empty()) continue;
+      const hipError_t q = hipEventQuery(e->lane[l].ev[e->lane[l].steps % A]);
+      if (q == hipSuccess) any = true;
+      else if (q != hipErrorNotReady) err = q;
+    }
+    if (!any && err == hipSuccess) std::this_thread::yield();
+  }
   std::vector<EheParams> he;
-  he.reserve((size_t)running);
-  bool need_table = false;
-  for (auto& g : groups) {
-    need_table = need_table || g.second.size() > (size_t)kInlineProblems;
-    for (int i : g.second) {
-      Slot& sl = e->slots[(size_t)i];
-      sense_plan p = sl.plan;
-      const CgArgs cg = p->cg_args(sl.tol, nullptr, 0);
-      he.emplace_back();
-      fill_ehe_cg_params(p->g, p->tb, p->maps, p->vectors(sl.x), sl.lambda, sl.k, cg, &he.back());
+  for (int l = 0; l < sense_engine_s::kLanes && err == hipSuccess; ++l) {
+    if (by_lane[(size_t)l].empty() || !has_room(l)) continue;
+    auto& ln = e->lane[l];
+    // newly joined slots: their admission work on the engine's stream first
+    long need = 0;
+    for (auto* g : by_lane[(size_t)l])
+      for (int i : g->second) need = std::max(need, e->slots[(size_t)i].admit_no);
+    if (need > ln.admits_seen) {
+      err = hipStreamWaitEvent(ln.st, e->admit_mark, 0);
+      ln.admits_seen = e->admits;
     }
-  }
-  if (need_table && err == hipSuccess) {
-    // groups larger than a kernel-argument table read a device copy; the
-    // staging buffer used two steps ago must have been consumed
-    const int b = e->buf;
-    err = hipEventSynchronize(e->staged[b]);
-    if (err == hipSuccess) {
-      std::copy(he.begin(), he.end(), e->h_ehe[b]);
-      err = hipMemcpyAsync(e->d_ehe, e->h_ehe[b], sizeof(EheParams) * he.size(), hipMemcpyHostToDevice, e->st);
-    }
-    if (err == hipSuccess) err = hipEventRecord(e->staged[b], e->st);
-    e->buf ^= 1;
-  }
-
-  // group 0 runs on the engine's stream, group i > 0 on side stream
-  // (i - 1) mod kLanes, forked after the table copy and joined before the
-  // step's event
-  constexpr int L = sense_engine_s::kLanes;
-  const int nlanes = std::min((int)groups.size() - 1, L);
-  if (nlanes > 0 && err == hipSuccess) {
-    err = hipEventRecord(e->fork, e->st);
-    for (int i = 0; i < nlanes && err == hipSuccess; ++i) err = hipStreamWaitEvent(e->lane[i], e->fork, 0);
-  }
-  int off = 0, gi = 0;
-  for (auto& g : groups) {
-    hipStream_t gs = gi == 0 ? e->st : e->lane[(gi - 1) % L];
-    ++gi;
-    const int cnt = (int)g.second.size();
-    int max_tiles = 0, max_groups = 1, max_ctiles = 0;
-    for (int j = 0; j < cnt; ++j) {
-      const EheParams& P = he[(size_t)(off + j)];
-      max_tiles = std::max(max_tiles, P.ntiles);
-      max_groups = std::max(max_groups, P.ngroups);
-      if (P.ngroups > 1) max_ctiles = std::max(max_ctiles, P.part_tiles);
-    }
-    // the fused launch also finishes each problem's previous iteration
-    if (cnt <= kInlineProblems) {
-      EheInline t{};
-      std::copy(he.begin() + off, he.begin() + off + cnt, t.p);
-      if (err == hipSuccess)
-        err = launch_ehe_inline(std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first), t, cnt,
-                                max_tiles, max_groups, gs);
-      if (err == hipSuccess && max_groups > 1) err = launch_combine_inline(t, cnt, max_ctiles, max_groups, gs);
-    } else {
-      if (err == hipSuccess)
-        err = launch_ehe_table(std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first), e->d_ehe + off,
-                               cnt, max_tiles, max_groups, gs);
-      if (err == hipSuccess && max_groups > 1) err = launch_combine_table(e->d_ehe + off, cnt, max_ctiles, max_groups, gs);
-    }
-    off += cnt;
-    for (int i : g.second) {
-      Slot& sl = e->slots[(size_t)i];
-      if (++sl.k == sl.K && err == hipSuccess) {
-        err = enqueue_solve_end(sl.plan, sl.x, sl.K, sl.plan->cg_args(sl.tol, nullptr, 0), nullptr, gs);
-        if (err == hipSuccess) err = hipEventRecord(sl.done, gs);
-        sl.finishing = true;
+    int toff = 0;  // this step's rows of the lane's device table
+    for (auto* g : by_lane[(size_t)l]) {
+      if (err != hipSuccess) break;
+      const int cnt = (int)g->second.size();
+      he.clear();
+      int max_tiles = 0, max_groups = 1, max_ctiles = 0;
+      for (int i : g->second) {
+        Slot& sl = e->slots[(size_t)i];
+        sense_plan p = sl.plan;
+        const CgArgs cg = p->cg_args(sl.tol, nullptr, 0);
+        he.emplace_back();
+        fill_ehe_cg_params(p->g, p->tb, p->maps, p->vectors(sl.x), sl.lambda, sl.k, cg, &he.back());
+        const EheParams& P = he.back();
+        max_tiles = std::max(max_tiles, P.ntiles);
+        max_groups = std::max(max_groups, P.ngroups);
+        if (P.ngroups > 1) max_ctiles = std::max(max_ctiles, P.part_tiles);
+      }
+      // the fused launch also finishes each problem's previous iteration
+      const long ny = std::get<0>(g->first);
+      const int mst = std::get<1>(g->first);
+      const bool staged = std::get<2>(g->first);
+      if (cnt <= kInlineProblems) {
+        EheInline t{};
+        std::copy(he.begin(), he.end(), t.p);
+        err = launch_ehe_inline(ny, mst, staged, t, cnt, max_tiles, max_groups, ln.st);
+        if (err == hipSuccess && max_groups > 1) err = launch_combine_inline(t, cnt, max_ctiles, max_groups, ln.st);
+      } else {
+        // larger groups read a device copy of the table; the staging
+        // buffer of this lane's step kAhead back was consumed (that step
+        // completed)
+        EheParams* h = ln.h_ehe[ln.steps % A] + toff;
+        EheParams* d = ln.d_ehe + toff;
+        std::copy(he.begin(), he.end(), h);
+        err = hipMemcpyAsync(d, h, sizeof(EheParams) * he.size(), hipMemcpyHostToDevice, ln.st);
+        if (err == hipSuccess) err = launch_ehe_table(ny, mst, staged, d, cnt, max_tiles, max_groups, ln.st);
+        if (err == hipSuccess && max_groups > 1) err = launch_combine_table(d, cnt, max_ctiles, max_groups, ln.st);
+        toff += cnt;
+      }
+      for (int i : g->second) {
+        Slot& sl = e->slots[(size_t)i];
+        if (++sl.k == sl.K && err == hipSuccess) {
+          err = enqueue_solve_end(sl.plan, sl.x, sl.K, sl.plan->cg_args(sl.tol, nullptr, 0), nullptr, ln.st);
+          if (err == hipSuccess) err = hipEventRecord(sl.done, ln.st);
+          sl.finishing = true;
+        }
       }
     }
+    if (err == hipSuccess) err = hipEventRecord(ln.ev[ln.steps % A], ln.st);
+    ++ln.steps;
   }
-  for (int i = 0; i < nlanes && err == hipSuccess; ++i) {
-    err = hipEventRecord(e->joined[i], e->lane[i]);
-    if (err == hipSuccess) err = hipStreamWaitEvent(e->st, e->joined[i], 0);
-  }
-  if (err == hipSuccess) err = hipEventRecord(e->stepped[e->steps % sense_engine_s::kAhead], e->st);
   ++e->steps;
   return err == hipSuccess ? SENSE_OK : device_fail(err, "sense_engine_step");
 }
@@ -317,7 +350,9 @@ sense_status sense_engine_poll(sense_engine e, int32_t* done_slots, int32_t max_
     if (q != hipSuccess) return device_fail(q, "sense_engine_poll");
     sl.plan->busy = false;
     e->used -= sl.footprint;
-    sl = Slot{false, false, nullptr, nullptr, nullptr, 0, 0, 0.0, 0.f, 0, sl.done};
+    const hipEvent_t done = sl.done;
+    sl = Slot{};
+    sl.done = done;
     done_slots[n++] = (int32_t)i;
   }
   *n_done = n;
@@ -338,7 +373,9 @@ sense_status sense_engine_stats(sense_engine e, size_t* used_bytes, size_t* budg
 
 sense_status sense_engine_sync(sense_engine e) {
   if (!e) return fail(SENSE_ERR_INVALID, "engine is NULL");
-  const hipError_t err = hipStreamSynchronize(e->st);
+  hipError_t err = hipStreamSynchronize(e->st);
+  for (auto& ln : e->lane)
+    if (err == hipSuccess) err = hipStreamSynchronize(ln.st);
   return err == hipSuccess ? SENSE_OK : device_fail(err, "sense_engine_sync");
 }
 

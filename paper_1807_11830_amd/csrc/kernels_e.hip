@@ -26,6 +26,7 @@
 #include "reduce.hpp"
 #include "xcd.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace sense {
@@ -92,7 +93,27 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
 }
 
 // Zero the listed rows of every (b, c) image (E writes zeros off the mask).
-// One block per line.
+// 16-byte streaming stores over (line, chunk) pairs, grid-stride: every
+// supported nx makes a line a whole number of 16-byte chunks, and the
+// launcher takes this path only for a 16-byte aligned k-space base.  The
+// zeros are written once and not read back by this operator, so they are
+// streamed past the caches.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) zero_rows16_kernel(char* out, const int32_t* rows, int nrows,
+                                                          long rows_total, long line_bytes, long lines) {
+  const long cpl = line_bytes / 16;
+  const long total = lines * cpl;
+  const u32x4 z = {0u, 0u, 0u, 0u};
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long)gridDim.x * 256) {
+    const long L = i / cpl, ch = i % cpl;
+    const long bc = L / nrows;
+    const long row = rows[L % nrows];
+    __builtin_nontemporal_store(z, reinterpret_cast<u32x4*>(out + (bc * rows_total + row) * line_bytes + ch * 16));
+  }
+}
+
+// The same with one element per store, for a k-space base that is not
+// 16-byte aligned.  One block per line.
 template <int ST>
 __global__ void zero_rows_kernel(void* out, const int32_t* rows, int nrows, long rows_total, long nx) {
   using TO = typename StorageT<ST>::T;
@@ -415,6 +436,14 @@ static hipError_t launch_zero_rows(const Geom& g, void* out, const int32_t* rows
                                    hipStream_t st) {
   if (nrows == 0) return hipSuccess;
   const long lines = (long)g.batch * g.ncoils * nrows;
+  const long line_bytes = g.nx * (long)sizeof(typename StorageT<ST>::T);
+  if (reinterpret_cast<uintptr_t>(out) % 16 == 0 && line_bytes % 16 == 0) {
+    const long chunks = lines * (line_bytes / 16);
+    const long blocks = std::min<long>((chunks + 255) / 256, 8192);
+    hipLaunchKernelGGL(zero_rows16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<char*>(out),
+                       rows, nrows, g.ny * g.nz, line_bytes, lines);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((zero_rows_kernel<ST>), dim3((unsigned)lines), dim3(256), 0, st, out, rows,
                      nrows, g.ny * g.nz, g.nx);
   return hipGetLastError();
