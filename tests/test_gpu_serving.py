@@ -88,6 +88,33 @@ def test_mixed_storage_groups_bitwise():
     assert not torch.equal(outs[0], outs[1])  # the storages really differ
 
 
+def test_shared_lanes_and_device_tables_bitwise():
+    """More group keys than the engine has lanes, two of them larger than a
+    kernel-argument table and sharing a lane (both read their rows of that
+    lane's device table in the same step); every result is bitwise its
+    plain solve."""
+    bank = InputBank()
+    spec = [(128, "c64")] * 17 + [(128, "bf16"), (192, "c64"), (192, "bf16")] + [(256, "c64")] * 17
+    reqs = [Request(i, 0.0, n, 8, 3, 6) for i, (n, _) in enumerate(spec)]
+    bank.prepare(reqs)
+    plans, ys, outs = [], [], []
+    for (n, st), r in zip(spec, reqs):
+        plans.append(sense.Plan(bank.coil_maps(n, 8), bank.mask(n, 3), maps_storage=st))
+        ys.append(bank.kspace(n, 8, 3))
+        outs.append(torch.empty((1, n, n), dtype=torch.complex64, device="cuda:0"))
+    with sense.Engine(budget_bytes=1 << 34, max_slots=48) as eng:
+        for i, p in enumerate(plans):
+            assert eng.admit(p, ys[i], outs[i], 6) == i
+        done = []
+        while len(done) < len(plans):
+            eng.step()
+            done += eng.poll()
+    for i, p in enumerate(plans):
+        ref = p.cg(ys[i], 6).x
+        assert torch.equal(outs[i], ref), (i, spec[i])
+        p.close()
+
+
 def test_mixed_requests_match_oracle():
     """A continuously batched stream of seeded requests (every request with
     its own maps, image and noise); three of them with different sizes and
