@@ -33,9 +33,21 @@ namespace sense {
 // compiler from moving LDS accesses across it.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <bool LB>
+// Exchanges whose partners all sit in one wavefront (the line's threads are
+// consecutive lanes of one wave): the wave's LDS operations are performed
+// in order, so waiting for its own writes (and keeping the compiler from
+// moving LDS accesses across the wait) is all an exchange needs; no block
+// barrier.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Synchronisation of the stage exchanges: a block barrier, an LDS-only
+// block barrier, or a wave-local wait.
+enum : int { kSyncBlock = 0, kSyncLds = 1, kSyncWave = 2 };
+
+template <int SY>
 __device__ __forceinline__ void exchange_barrier() {
-  if constexpr (LB) lds_barrier();
+  if constexpr (SY == kSyncLds) lds_barrier();
+  else if constexpr (SY == kSyncWave) wave_lds_sync();
   else __syncthreads();
 }
 
@@ -138,7 +150,7 @@ __device__ __forceinline__ void stockham_stage(c32* v, int t, const Tw& tw, View
 // exchange: the barrier in front of each exchange write keeps it behind the
 // previous exchange's reads (or the previous transform's), and the one after
 // it makes the write visible.
-template <int N, int T, int DIR, int NS, bool LB, class View, class Tw, int R, int... Rest>
+template <int N, int T, int DIR, int NS, int LB, class View, class Tw, int R, int... Rest>
 __device__ __forceinline__ void fft_stages(c32* v, int t, const Tw& tw, View b) {
   constexpr bool last = sizeof...(Rest) == 0;
   if constexpr (!last) exchange_barrier<LB>();
@@ -154,8 +166,9 @@ __device__ __forceinline__ void fft_stages(c32* v, int t, const Tw& tw, View b) 
 // Transform of one line held as v[j] = line[t + T j] by its T threads
 // (unnormalised; DIR = -1 forward, +1 inverse); the result returns to the
 // same positions.  b is the line's view of the LDS exchange buffer.  LB
-// selects LDS-only barriers for the exchanges (see lds_barrier).
-template <int N, int T, int DIR, bool LB = false, class View, class Tw, int... Rs>
+// selects the exchange synchronisation (exchange_barrier; a bool true is
+// kSyncLds).
+template <int N, int T, int DIR, int LB = kSyncBlock, class View, class Tw, int... Rs>
 __device__ __forceinline__ void fft_line(c32* v, int t, const Tw& tw, View b, Radices<Rs...>) {
   static_assert(radix_product(Radices<Rs...>{}) == N, "radices must multiply to N");
   fft_stages<N, T, DIR, 1, LB, View, Tw, Rs...>(v, t, tw, b);

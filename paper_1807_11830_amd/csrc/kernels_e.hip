@@ -83,7 +83,10 @@ __global__ void __launch_bounds__(ROW_NT) row_fft_kernel(RowParams P) {
   for (int j = 0; j < E; ++j) v[j] = cscale(load_c<ST_IN>(in, t + T * j), sgn);
   __syncthreads();
   PadLineView lv{&buf[l * LDL]};
-  fft_line<N, T, DIR>(v, t, TwTable{tw}, lv, Rad{});
+  // a line's T threads are consecutive lanes of one wave (T divides 64):
+  // its stage exchanges need no block barrier
+  static_assert(64 % T == 0, "a row line must sit inside one wavefront");
+  fft_line<N, T, DIR, kSyncWave>(v, t, TwTable{tw}, lv, Rad{});
   if (valid) {
     TO* out = static_cast<TO*>(P.out) + off_out;
     const float s = sgn * P.scale;
