@@ -71,7 +71,9 @@ constexpr int kCgParts = 3;
 struct CgArgs {
   CgState* state;        // [B]
   double* eta_part;      // [B][eta_tiles]
+  double* zeta_part;     // [B][eta_tiles] (3D: <q, q> partials of the normal operator)
   double* rr_part;       // [B][rr_tiles]
+  double* rr_par;        // 3D: [2][B][rr_tiles], <r, r> partials by iteration parity
   int eta_tiles;
   int rr_tiles;
   // fused 2D iteration: [2][B][part_stride][kCgParts] partials (Re<p,q>,
@@ -182,10 +184,17 @@ hipError_t launch_cg_fused_final(const Geom& g, const CgVectors& v, int K, const
 // CgState per batch element.
 hipError_t launch_cg_init(const Geom& g, const c32* b, c32* x, c32* r, c32* p, c32* q,
                           const CgArgs& cg, hipStream_t st);
-hipError_t launch_cg_update(const Geom& g, c32* x, c32* r, const c32* p, const c32* q,
-                            const CgArgs& cg, hipStream_t st);
 hipError_t launch_cg_finish(const Geom& g, const CgArgs& cg, CgInfo* info, CgInfo* info2, hipStream_t st);
-hipError_t launch_cg_pupdate(const Geom& g, const c32* r, c32* p, const CgArgs& cg, hipStream_t st);
+// 3D CG iteration k after q = A p (with the Re<p, q> and <q, q> partials):
+// the start-of-iteration tests on rho_k, then x += alpha p, r -= alpha q and
+// p = r + beta p with beta from alpha^2 <q, q> - rho_k, and the <r, r>
+// partials of the new residual.
+hipError_t launch_cg_update_fused(const Geom& g, c32* x, c32* r, c32* p, const c32* q, int k, const CgArgs& cg,
+                                  hipStream_t st);
+// The <r, r> partials the 3D update of iteration k reads (k == 0: the init
+// kernel's) and writes.
+const double* cg3_rr_in(const CgArgs& cg, int batch, int k);
+double* cg3_rr_out(const CgArgs& cg, int batch, int k);
 
 // Batched CG iteration over single-slice problems (serving engine): one
 // group launch over the table rows (grid z = the largest G), then one
@@ -233,9 +242,10 @@ hipError_t launch_EH(const Geom& g, const Tables& tb, const void* maps, const vo
 hipError_t launch_rss(const Geom& g, const Tables& tb, const void* y, c32* work, float* out, void* part,
                       int ngroups, hipStream_t st);
 // Normal operator from column passes (3D): q = E^H E p + lambda p, with the
-// readout transforms cancelled; fp64 partials of Re<p, q> per block.
+// readout transforms cancelled; fp64 partials of Re<p, q> and (zeta_part
+// non-null) <q, q> per block of the last pass.
 hipError_t launch_EHE_composed(const Geom& g, const Tables& tb, const void* maps, const c32* p, c32* q,
-                               c32* work, float lambda, double* eta_part, hipStream_t st);
+                               c32* work, float lambda, double* eta_part, double* zeta_part, hipStream_t st);
 // Blocks of the last composed pass per batch element (partials count).
 int adj_tiles(long nx, long ny, long nz);
 

@@ -1,16 +1,18 @@
 // Conjugate-gradient vector kernels for CG-SENSE (the normal equations
 // E^H E x = E^H y), one independent problem per batch element.
 //
-//   init    x = 0, p = r (= b = E^H y), partial <r, r>;  state reset
-//   update  alpha = rho_k / eta with eta = Re<p, q> summed from the fused
-//           E^H E partials; x += alpha p, r -= alpha q, partial <r, r>
-//   finish  final tolerance test and per-problem info
+//   init          x = 0, p = r (= b = E^H y), partial <r, r>;  state reset
+//   fused final   2D: the updates of the last fused iteration (x, r) and
+//                 the partials of <r, r> for the final test
+//   update fused  3D: the tests of iteration k, then x, r and p updates and
+//                 the <r, r> partials (one reduction per iteration)
+//   finish        final tolerance test and per-problem info
+//   combine       2D coil groups: the group partials of q added in order
 //
-// The fused E^H E launch of the next iteration sums the <r, r> partials
-// itself and forms p = r + beta p.  Inner products, alpha and beta are fp64;
-// vectors are fp32 complex.  Every block of a batch element reduces the same
-// partials in the same order, so all blocks take the same decisions and the
-// results do not depend on scheduling.
+// Inner products, alpha and beta are fp64; vectors are fp32 complex.  Every
+// block of a batch element reduces the same partials in the same order, so
+// all blocks take the same decisions and the results do not depend on
+// scheduling.
 #include "bufio.hpp"
 #include "cg_scalar.hpp"
 #include "kernels.hpp"
@@ -62,21 +64,57 @@ __global__ void __launch_bounds__(CG_NT) cg_init_kernel(const c32* __restrict__ 
   }
 }
 
-__device__ __forceinline__ void cg_update_body(c32* __restrict__ x, c32* __restrict__ r,
-                                               const c32* __restrict__ p, const c32* __restrict__ q,
-                                               long nvox, const CgArgs& cg, const int b, const int tile) {
+// The <r, r> partials of the 3D iterations: launch k reads those of r_k
+// (the init kernel's for k = 0, else parity buffer (k - 1) & 1) and writes
+// those of r_(k+1) into parity buffer k & 1, so no launch overwrites
+// partials that its own blocks still read.
+const double* cg3_rr_in(const CgArgs& cg, int batch, int k) {
+  return k == 0 ? cg.rr_part : cg.rr_par + (long)((k - 1) & 1) * batch * cg.rr_tiles;
+}
+double* cg3_rr_out(const CgArgs& cg, int batch, int k) {
+  return cg.rr_par + (long)(k & 1) * batch * cg.rr_tiles;
+}
+
+// 3D CG iteration k, after q = A p left the partials of eta = Re<p, q> and
+// zeta = <q, q>.  Every block sums rho_k (the true <r_k, r_k>), eta and zeta
+// from the same partials in the same order and takes the textbook loop's
+// decisions on them: rho_k non-finite, the tolerance (k > 0), rho_k == 0,
+// then eta non-finite or <= 0.  Then alpha = rho_k / eta, x += alpha p,
+// r -= alpha q, p = r + beta p with beta = (alpha^2 zeta - rho_k) / rho_k,
+// the exact <r - alpha q, r - alpha q> / rho_k under A-conjugacy (the fused
+// 2D iteration uses the same form), and the <r, r> partials of the new
+// residual, which re-anchor the next launch.  The iteration index comes
+// from the launch, not from the state (which this launch advances).
+__global__ void __launch_bounds__(CG_NT) cg_update_fused_kernel(c32* __restrict__ x, c32* __restrict__ r,
+                                                                c32* __restrict__ p, const c32* __restrict__ q,
+                                                                long nvox, int k, const double* __restrict__ rr_in,
+                                                                double* __restrict__ rr_out, CgArgs cg) {
   __shared__ double red[CG_NT / 64];
+  const int b = blockIdx.y;
+  const int tile = blockIdx.x;
   CgState* st = cg.state + b;
   if (st->status != CG_RUNNING) return;
+  const double rho = ordered_sum(rr_in + (long)b * cg.rr_tiles, cg.rr_tiles);
   const double eta = ordered_sum(cg.eta_part + (long)b * cg.eta_tiles, cg.eta_tiles);
+  const double zeta = ordered_sum(cg.zeta_part + (long)b * cg.eta_tiles, cg.eta_tiles);
+  const double rho0 = k == 0 ? rho : st->rho0;
   int stop = CG_RUNNING;
-  if (!finite64(eta)) stop = CG_NONFINITE;
+  if (!finite64(rho)) stop = CG_NONFINITE;
+  else if (k > 0 && cg.tol > 0.0 && sqrt(rho / rho0) < cg.tol) stop = CG_CONVERGED;
+  else if (rho == 0.0) stop = CG_EXACT;
+  else if (!finite64(eta)) stop = CG_NONFINITE;
   else if (eta <= 0.0) stop = CG_BREAKDOWN;
-  if (stop != CG_RUNNING) {
-    if (tile == 0 && threadIdx.x == 0) st->status = stop;
-    return;
+  if (tile == 0 && threadIdx.x == 0) {
+    if (k == 0) st->rho0 = rho;
+    st->rho[k & 1] = rho;
+    st->rho_cur = rho;
+    if (cg.rho_hist && k < cg.hist_len) cg.rho_hist[(long)b * cg.hist_len + k] = rho;
+    if (stop != CG_RUNNING) st->status = stop;
+    else st->iter = k + 1;
   }
-  const double alpha = st->rho_cur / eta;
+  if (stop != CG_RUNNING) return;
+  const double alpha = rho / eta;
+  const double beta = (alpha * alpha * zeta - rho) / rho;
 
   const long base = (long)b * nvox + (long)tile * CG_CHUNK;
   const long lim = (long)b * nvox + nvox;
@@ -87,7 +125,7 @@ __device__ __forceinline__ void cg_update_body(c32* __restrict__ x, c32* __restr
     if (i < lim) {
       c32x2 xv = *reinterpret_cast<const c32x2*>(x + i);
       c32x2 rv = *reinterpret_cast<const c32x2*>(r + i);
-      const c32x2 pv = *reinterpret_cast<const c32x2*>(p + i);
+      c32x2 pv = *reinterpret_cast<const c32x2*>(p + i);
       const c32x2 qv = *reinterpret_cast<const c32x2*>(q + i);
       xv.a.re = (float)((double)xv.a.re + alpha * pv.a.re);
       xv.a.im = (float)((double)xv.a.im + alpha * pv.a.im);
@@ -97,24 +135,19 @@ __device__ __forceinline__ void cg_update_body(c32* __restrict__ x, c32* __restr
       rv.a.im = (float)((double)rv.a.im - alpha * qv.a.im);
       rv.b.re = (float)((double)rv.b.re - alpha * qv.b.re);
       rv.b.im = (float)((double)rv.b.im - alpha * qv.b.im);
+      pv.a.re = (float)((double)rv.a.re + beta * pv.a.re);
+      pv.a.im = (float)((double)rv.a.im + beta * pv.a.im);
+      pv.b.re = (float)((double)rv.b.re + beta * pv.b.re);
+      pv.b.im = (float)((double)rv.b.im + beta * pv.b.im);
       *reinterpret_cast<c32x2*>(x + i) = xv;
       *reinterpret_cast<c32x2*>(r + i) = rv;
+      *reinterpret_cast<c32x2*>(p + i) = pv;
       acc += (double)rv.a.re * rv.a.re + (double)rv.a.im * rv.a.im + (double)rv.b.re * rv.b.re +
              (double)rv.b.im * rv.b.im;
     }
   }
   const double tot = block_sum<CG_NT>(acc, red);
-  if (threadIdx.x == 0) {
-    cg.rr_part[(long)b * cg.rr_tiles + tile] = tot;
-    if (tile == 0) st->iter = st->iter + 1;
-  }
-}
-
-__global__ void __launch_bounds__(CG_NT) cg_update_kernel(c32* __restrict__ x, c32* __restrict__ r,
-                                                          const c32* __restrict__ p,
-                                                          const c32* __restrict__ q, long nvox,
-                                                          CgArgs cg) {
-  cg_update_body(x, r, p, q, nvox, cg, blockIdx.y, blockIdx.x);
+  if (threadIdx.x == 0) rr_out[(long)b * cg.rr_tiles + tile] = tot;
 }
 
 __global__ void __launch_bounds__(64) cg_finish_kernel(CgArgs cg, CgInfo* info, CgInfo* info2) {
@@ -148,32 +181,6 @@ __global__ void __launch_bounds__(64) cg_finish_kernel(CgArgs cg, CgInfo* info, 
   o.rho_final = rho_final;
   if (info) info[b] = o;
   if (info2) info2[b] = o;
-}
-
-// p = r + beta p with the start-of-iteration scalar logic (used where the
-// normal operator is not the fused 2D kernel).
-__global__ void __launch_bounds__(CG_NT) cg_pupdate_kernel(const c32* __restrict__ r, c32* __restrict__ p,
-                                                           long nvox, CgArgs cg) {
-  const int b = blockIdx.y;
-  double beta = 0.0;
-  if (!cg_iteration_begin(cg.state + b, cg.rr_part, cg.rr_tiles, cg.rho_hist, cg.hist_len, cg.tol, b,
-                          blockIdx.x == 0 && threadIdx.x == 0, beta))
-    return;
-  const long base = (long)b * nvox + (long)blockIdx.x * CG_CHUNK;
-  const long lim = (long)b * nvox + nvox;
-#pragma unroll
-  for (int s = 0; s < CG_STEPS; ++s) {
-    const long i = base + ((long)s * CG_NT + threadIdx.x) * CG_VEC;
-    if (i < lim) {
-      const c32x2 rv = *reinterpret_cast<const c32x2*>(r + i);
-      c32x2 pv = *reinterpret_cast<const c32x2*>(p + i);
-      pv.a.re = (float)((double)rv.a.re + beta * pv.a.re);
-      pv.a.im = (float)((double)rv.a.im + beta * pv.a.im);
-      pv.b.re = (float)((double)rv.b.re + beta * pv.b.re);
-      pv.b.im = (float)((double)rv.b.im + beta * pv.b.im);
-      *reinterpret_cast<c32x2*>(p + i) = pv;
-    }
-  }
 }
 
 // Last step of the fused 2D iteration: launch K's scalar logic, then
@@ -367,13 +374,6 @@ hipError_t launch_combine_table(const EheParams* d_table, int nproblems, int max
   return hipGetLastError();
 }
 
-hipError_t launch_cg_pupdate(const Geom& g, const c32* r, c32* p, const CgArgs& cg, hipStream_t st) {
-  const long nvox = g.nx * g.ny * g.nz;
-  dim3 grid((unsigned)cg_tiles(nvox), (unsigned)g.batch);
-  hipLaunchKernelGGL(cg_pupdate_kernel, grid, dim3(CG_NT), 0, st, r, p, nvox, cg);
-  return hipGetLastError();
-}
-
 hipError_t launch_cg_init(const Geom& g, const c32* bvec, c32* x, c32* r, c32* p, c32* q, const CgArgs& cg,
                           hipStream_t st) {
   const long nvox = g.nx * g.ny * g.nz;
@@ -382,11 +382,12 @@ hipError_t launch_cg_init(const Geom& g, const c32* bvec, c32* x, c32* r, c32* p
   return hipGetLastError();
 }
 
-hipError_t launch_cg_update(const Geom& g, c32* x, c32* r, const c32* p, const c32* q,
-                            const CgArgs& cg, hipStream_t st) {
+hipError_t launch_cg_update_fused(const Geom& g, c32* x, c32* r, c32* p, const c32* q, int k, const CgArgs& cg,
+                                  hipStream_t st) {
   const long nvox = g.nx * g.ny * g.nz;
   dim3 grid((unsigned)cg_tiles(nvox), (unsigned)g.batch);
-  hipLaunchKernelGGL(cg_update_kernel, grid, dim3(CG_NT), 0, st, x, r, p, q, nvox, cg);
+  hipLaunchKernelGGL(cg_update_fused_kernel, grid, dim3(CG_NT), 0, st, x, r, p, q, nvox, k,
+                     cg3_rr_in(cg, g.batch, k), cg3_rr_out(cg, g.batch, k), cg);
   return hipGetLastError();
 }
 

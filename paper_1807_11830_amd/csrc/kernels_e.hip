@@ -145,6 +145,7 @@ struct ColPass {
   c32* dst;
   const c32* addp;     // ADJ_COIL: p for lambda p and eta (may be null)
   double* eta_part;    // ADJ_COIL: [b][gridDim.x * gridDim.y] (may be null)
+  double* zeta_part;   // ADJ_COIL: <q, q> partials, same layout (may be null)
   const uint8_t* mask; // centred [nz][ny]
   const c32* tw;
   long nx, ny, nz;
@@ -304,7 +305,7 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
       return;
     }
     const Buf bd = make_buf(P.dst + b * nvox, vbytes);
-    double eta = 0.0;
+    double eta = 0.0, zeta = 0.0;
     // p for lambda p and Re<p, q>: all loads first (an out-of-range offset
     // when there is no p), so no wait falls between two of them
     const Buf bp = make_buf(P.addp ? P.addp + b * nvox : P.dst, vbytes);
@@ -317,12 +318,20 @@ __global__ void __launch_bounds__((Len<N>::T * pass_tile<Len<N>::T, AXIS>())) co
       c32 qq = cscale(acc[j], P.scale);
       qq = {qq.re + P.lambda * pv[j].re, qq.im + P.lambda * pv[j].im};
       eta += (double)pv[j].re * (double)qq.re + (double)pv[j].im * (double)qq.im;
+      zeta += (double)qq.re * (double)qq.re + (double)qq.im * (double)qq.im;
       if (valid) buf_store_c64<CPW>(bd, qq, o, 0);
     }
+    const long pidx = b * (long)gridDim.x * gridDim.y + (long)id.y * gridDim.x + id.x;
     if (P.eta_part) {
       if (!valid) eta = 0.0;
       const double tot = block_sum<NT>(eta, red);
-      if (tid == 0) P.eta_part[b * (long)gridDim.x * gridDim.y + (long)id.y * gridDim.x + id.x] = tot;
+      if (tid == 0) P.eta_part[pidx] = tot;
+    }
+    if (P.zeta_part) {
+      if (!valid) zeta = 0.0;
+      if (P.eta_part) __syncthreads();  // red is reused
+      const double tot = block_sum<NT>(zeta, red);
+      if (tid == 0) P.zeta_part[pidx] = tot;
     }
   }
 }
@@ -614,7 +623,7 @@ hipError_t launch_EH(const Geom& g, const Tables& tb, const void* maps, const vo
 // (ky, x) line, y inverse with the conjugate-sensitivity coil sum.  Each
 // centred axis pair contributes 1/n, applied once: scale 1/(ny nz).
 hipError_t launch_EHE_composed(const Geom& g, const Tables& tb, const void* maps, const c32* p, c32* q,
-                               c32* work, float lambda, double* eta_part, hipStream_t st) {
+                               c32* work, float lambda, double* eta_part, double* zeta_part, hipStream_t st) {
   ColPass P{};
   P.maps = maps;
   P.src = p;
@@ -641,6 +650,7 @@ hipError_t launch_EHE_composed(const Geom& g, const Tables& tb, const void* maps
   A.addp = p;
   A.lambda = lambda;
   A.eta_part = eta_part;
+  A.zeta_part = zeta_part;
   A.mask = tb.mask_c;
   A.tw = tb.tw_y;
   A.mask_load = g.nz > 1 ? 0 : 1;

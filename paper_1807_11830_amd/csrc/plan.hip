@@ -95,7 +95,9 @@ Layout make_layout(const sense_desc& d) {
   L.qpart = L.ngroups > 1 ? take(sizeof(c32) * (size_t)L.ngroups * B * nvox) : 0;
   L.state = take(sizeof(CgState) * B);
   L.eta_part = take(sizeof(double) * B * (size_t)L.eta_tiles);
+  L.zeta_part = take(sizeof(double) * B * (size_t)L.eta_tiles);
   L.rr_part = take(sizeof(double) * B * (size_t)L.rr_tiles);
+  L.rr_par = take(sizeof(double) * 2 * B * (size_t)L.rr_tiles);
   const size_t ptiles = (size_t)std::max(L.eta_tiles, L.rr_tiles);
   L.cgpart = take(sizeof(double) * 2 * B * ptiles * kCgParts);
   L.info = take(sizeof(CgInfo) * B);
@@ -246,11 +248,12 @@ hipError_t enqueue_iteration(sense_plan p, c32* x, float lambda, int k, const Cg
   if (timed_ehe_begin(p, st, &stop) != SENSE_OK) return hipErrorUnknown;
   hipError_t e;
   if (p->d.ndim == 3) {
-    e = launch_cg_pupdate(p->g, r, pv, cg, st);
-    if (e == hipSuccess)
-      e = launch_EHE_composed(p->g, p->tb, p->maps, pv, q, p->at<c32>(p->L.work), lambda, cg.eta_part, st);
+    // q = A p with the Re<p, q> and <q, q> partials, then one update of x,
+    // r and p (single reduction, as in the fused 2D iteration)
+    e = launch_EHE_composed(p->g, p->tb, p->maps, pv, q, p->at<c32>(p->L.work), lambda, cg.eta_part,
+                            cg.zeta_part, st);
     if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
-    if (e == hipSuccess) e = launch_cg_update(p->g, x, r, pv, q, cg, st);
+    if (e == hipSuccess) e = launch_cg_update_fused(p->g, x, r, pv, q, k, cg, st);
   } else {
     // one launch (plus the combine pass with coil groups): the updates of
     // iteration k-1 fused in front of q = A p
@@ -263,7 +266,10 @@ hipError_t enqueue_iteration(sense_plan p, c32* x, float lambda, int k, const Cg
 hipError_t enqueue_solve_end(sense_plan p, c32* x, int K, const CgArgs& cg, CgInfo* d_info, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (p->d.ndim != 3 && K > 0) e = launch_cg_fused_final(p->g, p->vectors(x), K, cg, st);
-  if (e == hipSuccess) e = launch_cg_finish(p->g, cg, p->at<CgInfo>(p->L.info), d_info, st);
+  // 3D: the last update left rho_K's partials in its parity buffer
+  CgArgs cf = cg;
+  if (p->d.ndim == 3) cf.rr_part = const_cast<double*>(cg3_rr_in(cg, p->d.batch, K));
+  if (e == hipSuccess) e = launch_cg_finish(p->g, cf, p->at<CgInfo>(p->L.info), d_info, st);
   return e;
 }
 
@@ -450,7 +456,7 @@ sense_status sense_apply_EHE(sense_plan p, const void* d_p, void* d_q, double la
   hipError_t e = p->d.ndim == 3
                      ? launch_EHE_composed(p->g, p->tb, p->maps, static_cast<const c32*>(d_p),
                                            static_cast<c32*>(d_q), p->at<c32>(p->L.work), (float)lambda,
-                                           p->at<double>(p->L.eta_part), st)
+                                           p->at<double>(p->L.eta_part), nullptr, st)
                      : launch_ehe(p->g, p->tb, p->maps, static_cast<const c32*>(d_p), static_cast<c32*>(d_q),
                                   (float)lambda, nullptr, p->at<c32>(p->L.qpart), p->ngroups, st);
   if (stop && e == hipSuccess) e = hipEventRecord(stop, st);

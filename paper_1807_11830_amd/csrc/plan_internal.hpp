@@ -14,7 +14,7 @@ namespace sense {
 struct Layout {
   size_t tw_x, tw_y, tw_z, mu_y, mask_c, rows_s, rows_u;
   size_t work, r, p, q, r2, p2, qpart;
-  size_t state, eta_part, rr_part, cgpart, info;
+  size_t state, eta_part, zeta_part, rr_part, rr_par, cgpart, info;
   size_t total;
   int eta_tiles, rr_tiles;
   int ngroups;   // coil groups the workspace holds (the fill split)
@@ -100,7 +100,9 @@ struct sense_plan_s {
     CgArgs a{};
     a.state = at<sense::CgState>(L.state);
     a.eta_part = at<double>(L.eta_part);
+    a.zeta_part = at<double>(L.zeta_part);
     a.rr_part = at<double>(L.rr_part);
+    a.rr_par = at<double>(L.rr_par);
     a.eta_tiles = L.eta_tiles;
     a.rr_tiles = L.rr_tiles;
     a.cgpart = at<double>(L.cgpart);

@@ -110,6 +110,37 @@ def test_3d_cg_matches_oracle():
     assert np.allclose(res.rho_hist.cpu().numpy()[0, :4], hist[0, :4], rtol=1e-5)
 
 
+def test_3d_cg_tolerance_stop_and_batch():
+    """3D CG with a relative tolerance on a batch of two problems (per-slice
+    maps): the iteration count and status of each element, its rho history
+    and x against the oracle's loop; and the same problem with a zero
+    right-hand side in the second element stops with EXACT at iteration 0."""
+    nz, ny, nx, nc, B = 8, 32, 16, 4, 2
+    base = synth.coil_maps3d(nx, ny, nz, nc)
+    maps = c64(np.stack([base * np.exp(0.3j * b * np.arange(1, nc + 1))[:, None, None, None] for b in range(B)]))
+    mask = synth.mask_variable_density_2d(ny, nz, 2.5, (8, 4))
+    xt = np.concatenate([synth.phantom3d(nx, ny, nz, seed=20 + b)[None] for b in range(B)])
+    y = np.concatenate([oracle.E(xt[b:b + 1], maps[b], mask, ndim=3) for b in range(B)])
+    y = c64(y + synth.complex_noise(y.shape) * mask[None, None, :, :, None])
+    tol, K = 3.4e-3, 40  # both elements cross it with a margin of at least 10%
+    with sense.Plan(to_dev(maps), mask, batch=B) as plan:
+        res = plan.cg(to_dev(y), K, tol=tol, history=True)
+        for b in range(B):
+            xo, it, st, hist = oracle.cg(y[b:b + 1], maps[b], mask, K, tol=tol, ndim=3)
+            err = rel_l2(to_host(res.x[b:b + 1]), xo)
+            log(f"3D CG tol: element {b} iters {res.iters[b]} (oracle {it[0]}), status {res.status[b]}, rel-L2 {err:.3e}")
+            assert res.iters[b] == it[0] < K and res.status[b] == st[0] == sense.CONVERGED
+            n = int(it[0]) + 1
+            assert np.allclose(res.rho_hist.cpu().numpy()[b, :n], hist[0, :n], rtol=1e-4)
+            assert err <= 1e-4
+        y0 = y.copy()
+        y0[1] = 0
+        res0 = plan.cg(to_dev(y0), K, tol=tol)
+    assert res0.status[1] == sense.EXACT and res0.iters[1] == 0
+    assert not np.any(to_host(res0.x[1:2]))
+    assert res0.iters[0] == res.iters[0] and res0.status[0] == sense.CONVERGED
+
+
 def _loss_and_grad(plan, x, y):
     xt = to_dev(x).requires_grad_(True)
     r = sense_E(xt, plan) - to_dev(y)
