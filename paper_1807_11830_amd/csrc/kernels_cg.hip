@@ -13,6 +13,8 @@
 // block of a batch element reduces the same partials in the same order, so
 // all blocks take the same decisions and the results do not depend on
 // scheduling.
+#include <algorithm>
+
 #include "bufio.hpp"
 #include "cg_scalar.hpp"
 #include "kernels.hpp"
@@ -85,13 +87,17 @@ double* cg3_rr_out(const CgArgs& cg, int batch, int k) {
 // 2D iteration uses the same form), and the <r, r> partials of the new
 // residual, which re-anchor the next launch.  The iteration index comes
 // from the launch, not from the state (which this launch advances).
+// A block sums the partials once (thousands of them at 3D sizes, a
+// latency-bound preamble) and then strides over the CG_CHUNK tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ..., writing each tile's <r, r>
+// partial, so the partial layout is that of the init kernel.
+constexpr int kUpdateMaxBlocks = 1024;
 __global__ void __launch_bounds__(CG_NT) cg_update_fused_kernel(c32* __restrict__ x, c32* __restrict__ r,
                                                                 c32* __restrict__ p, const c32* __restrict__ q,
                                                                 long nvox, int k, const double* __restrict__ rr_in,
                                                                 double* __restrict__ rr_out, CgArgs cg) {
   __shared__ double red[CG_NT / 64];
   const int b = blockIdx.y;
-  const int tile = blockIdx.x;
   CgState* st = cg.state + b;
   if (st->status != CG_RUNNING) return;
   const double rho = ordered_sum(rr_in + (long)b * cg.rr_tiles, cg.rr_tiles);
@@ -104,7 +110,7 @@ __global__ void __launch_bounds__(CG_NT) cg_update_fused_kernel(c32* __restrict_
   else if (rho == 0.0) stop = CG_EXACT;
   else if (!finite64(eta)) stop = CG_NONFINITE;
   else if (eta <= 0.0) stop = CG_BREAKDOWN;
-  if (tile == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (k == 0) st->rho0 = rho;
     st->rho[k & 1] = rho;
     st->rho_cur = rho;
@@ -116,38 +122,41 @@ __global__ void __launch_bounds__(CG_NT) cg_update_fused_kernel(c32* __restrict_
   const double alpha = rho / eta;
   const double beta = (alpha * alpha * zeta - rho) / rho;
 
-  const long base = (long)b * nvox + (long)tile * CG_CHUNK;
-  const long lim = (long)b * nvox + nvox;
-  double acc = 0.0;
+  for (int tile = blockIdx.x; tile < cg.rr_tiles; tile += gridDim.x) {
+    const long base = (long)b * nvox + (long)tile * CG_CHUNK;
+    const long lim = (long)b * nvox + nvox;
+    double acc = 0.0;
 #pragma unroll
-  for (int s = 0; s < CG_STEPS; ++s) {
-    const long i = base + ((long)s * CG_NT + threadIdx.x) * CG_VEC;
-    if (i < lim) {
-      c32x2 xv = *reinterpret_cast<const c32x2*>(x + i);
-      c32x2 rv = *reinterpret_cast<const c32x2*>(r + i);
-      c32x2 pv = *reinterpret_cast<const c32x2*>(p + i);
-      const c32x2 qv = *reinterpret_cast<const c32x2*>(q + i);
-      xv.a.re = (float)((double)xv.a.re + alpha * pv.a.re);
-      xv.a.im = (float)((double)xv.a.im + alpha * pv.a.im);
-      xv.b.re = (float)((double)xv.b.re + alpha * pv.b.re);
-      xv.b.im = (float)((double)xv.b.im + alpha * pv.b.im);
-      rv.a.re = (float)((double)rv.a.re - alpha * qv.a.re);
-      rv.a.im = (float)((double)rv.a.im - alpha * qv.a.im);
-      rv.b.re = (float)((double)rv.b.re - alpha * qv.b.re);
-      rv.b.im = (float)((double)rv.b.im - alpha * qv.b.im);
-      pv.a.re = (float)((double)rv.a.re + beta * pv.a.re);
-      pv.a.im = (float)((double)rv.a.im + beta * pv.a.im);
-      pv.b.re = (float)((double)rv.b.re + beta * pv.b.re);
-      pv.b.im = (float)((double)rv.b.im + beta * pv.b.im);
-      *reinterpret_cast<c32x2*>(x + i) = xv;
-      *reinterpret_cast<c32x2*>(r + i) = rv;
-      *reinterpret_cast<c32x2*>(p + i) = pv;
-      acc += (double)rv.a.re * rv.a.re + (double)rv.a.im * rv.a.im + (double)rv.b.re * rv.b.re +
-             (double)rv.b.im * rv.b.im;
+    for (int s = 0; s < CG_STEPS; ++s) {
+      const long i = base + ((long)s * CG_NT + threadIdx.x) * CG_VEC;
+      if (i < lim) {
+        c32x2 xv = *reinterpret_cast<const c32x2*>(x + i);
+        c32x2 rv = *reinterpret_cast<const c32x2*>(r + i);
+        c32x2 pv = *reinterpret_cast<const c32x2*>(p + i);
+        const c32x2 qv = *reinterpret_cast<const c32x2*>(q + i);
+        xv.a.re = (float)((double)xv.a.re + alpha * pv.a.re);
+        xv.a.im = (float)((double)xv.a.im + alpha * pv.a.im);
+        xv.b.re = (float)((double)xv.b.re + alpha * pv.b.re);
+        xv.b.im = (float)((double)xv.b.im + alpha * pv.b.im);
+        rv.a.re = (float)((double)rv.a.re - alpha * qv.a.re);
+        rv.a.im = (float)((double)rv.a.im - alpha * qv.a.im);
+        rv.b.re = (float)((double)rv.b.re - alpha * qv.b.re);
+        rv.b.im = (float)((double)rv.b.im - alpha * qv.b.im);
+        pv.a.re = (float)((double)rv.a.re + beta * pv.a.re);
+        pv.a.im = (float)((double)rv.a.im + beta * pv.a.im);
+        pv.b.re = (float)((double)rv.b.re + beta * pv.b.re);
+        pv.b.im = (float)((double)rv.b.im + beta * pv.b.im);
+        *reinterpret_cast<c32x2*>(x + i) = xv;
+        *reinterpret_cast<c32x2*>(r + i) = rv;
+        *reinterpret_cast<c32x2*>(p + i) = pv;
+        acc += (double)rv.a.re * rv.a.re + (double)rv.a.im * rv.a.im + (double)rv.b.re * rv.b.re +
+               (double)rv.b.im * rv.b.im;
+      }
     }
+    const double tot = block_sum<CG_NT>(acc, red);
+    if (threadIdx.x == 0) rr_out[(long)b * cg.rr_tiles + tile] = tot;
+    __syncthreads();  // red is reused by the next tile
   }
-  const double tot = block_sum<CG_NT>(acc, red);
-  if (threadIdx.x == 0) rr_out[(long)b * cg.rr_tiles + tile] = tot;
 }
 
 __global__ void __launch_bounds__(64) cg_finish_kernel(CgArgs cg, CgInfo* info, CgInfo* info2) {
@@ -385,7 +394,7 @@ hipError_t launch_cg_init(const Geom& g, const c32* bvec, c32* x, c32* r, c32* p
 hipError_t launch_cg_update_fused(const Geom& g, c32* x, c32* r, c32* p, const c32* q, int k, const CgArgs& cg,
                                   hipStream_t st) {
   const long nvox = g.nx * g.ny * g.nz;
-  dim3 grid((unsigned)cg_tiles(nvox), (unsigned)g.batch);
+  dim3 grid((unsigned)std::min(cg_tiles(nvox), kUpdateMaxBlocks), (unsigned)g.batch);
   hipLaunchKernelGGL(cg_update_fused_kernel, grid, dim3(CG_NT), 0, st, x, r, p, q, nvox, k,
                      cg3_rr_in(cg, g.batch, k), cg3_rr_out(cg, g.batch, k), cg);
   return hipGetLastError();
