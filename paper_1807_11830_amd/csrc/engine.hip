@@ -64,9 +64,9 @@ struct sense_engine_s {
   // steps, and its own table buffers for groups larger than a
   // kernel-argument table (device copy, two pinned staging buffers used by
   // alternate steps)
-  // (measured with one shared bound: 2 and 4 steps ahead give the same
-  // latencies; without a bound the queue behind a new request grows with
-  // the load)
+  // (measured per lane: 2 and 4 steps ahead give the same latencies within
+  // run-to-run noise; without a bound the queue behind a new request grows
+  // with the load)
   static constexpr int kAhead = 2;
   static constexpr int kLanes = 4;
   struct Lane {
