@@ -70,9 +70,9 @@ constexpr bool ehe_stage_maps() {
 // and the memory-side cache between launches lose their hits (one 256^2
 // slice with 16 coils: 26.2 -> 28.0 us; 16 slices of 320^2 with 32 coils,
 // 0.52 GB: 238 -> 240 us).  Plan launches stream from kStreamBytes of
-// algorithmic traffic on; batched serving launches never do.  Lengths
-// below 128 points are never part of such a launch's shape here, so only
-// 128 points and up have streaming instantiations.
+// algorithmic traffic on; batched serving launches never do.  Streaming
+// instantiations exist from 128 points on (smaller slices reach 1 GiB per
+// launch only at batches of thousands, which take the default policy).
 template <int N, int SB>
 constexpr int ehe_cache_policy() {
   return EheLen<N>::TX * SB >= 128 ? kCacheStream : kCacheDefault;
