@@ -676,7 +676,9 @@ def run_cgsense(args):
         "roofline": {"bound": "hbm", "kernel": "ehe2d_kernel (fused CG iteration: x, r, p updates + E^H E)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("sense::ehe2d_kernel<256, 0, true, false, true>"),
+                     # counters were taken for the complex64-maps instantiation only
+                     "traffic": measured_traffic("sense::ehe2d_kernel<256, 0, true, false, true>")
+                     if args.maps_storage == "c64" else None,
                      "avg_launch_us": avg_s * 1e6, "launches": n_l,
                      "bytes_per_launch": round(bytes_launch)},
         "ehe_apply": {"avg_launch_us": apply_s * 1e6, "bytes_per_launch": apply_bytes,
