@@ -12,6 +12,23 @@
 // replaces the per-iteration launches whose latency dominates a small
 // solve.  The launch after E^H y (which has written b into r) is the whole
 // solve, including the per-problem info.
+//
+// Two thread layouts.  With wave-local lines (WL) the T threads of a column
+// are consecutive lanes of one wavefront and every column has its own LDS
+// line, so the transform's exchanges need no block barrier and the only
+// block barriers of an iteration are those of the two inner products.
+// Otherwise a wavefront spans 64 columns at one row offset (whole-line map
+// reads) and the exchanges take block barriers.  With at most
+// kSmallRegCoils coils and at most 8 elements per thread the sensitivity
+// maps are read once, before the first iteration, and held in registers
+// (MREG); otherwise each iteration reads them again (from L2).  Measured on
+// MI355X, 20 iterations of one slice: 64^2 with 4 coils 172.8 us with the
+// maps re-read and the block layout, 129.6 us with the maps in registers and
+// wave-local lines, 145.1 us with the maps in registers and the block
+// layout.  Without MREG wave-local lines are faster except for complex64
+// maps at 64 rows (wave-local against block layout: 48^2 x 8 coils, BF16
+// maps, 272 against 319 us; 64^2 x 8 coils, complex64 maps, 333 against
+// 298 us).
 #include "bufio.hpp"
 #include "kernels.hpp"
 #include "lengths.hpp"
@@ -20,6 +37,7 @@
 namespace sense {
 
 constexpr int kSmallCols = 64;  // columns per workgroup: the whole slice
+constexpr int kSmallRegCoils = 4;
 
 struct SmallParams {
   const void* maps;
@@ -45,35 +63,79 @@ constexpr bool small_len() {
   return N == 8 || N == 16 || N == 32 || N == 48 || N == 64;
 }
 
-// Sum of v over the block, returned to every thread (fixed order).
+// Sum of v over the block, returned to every thread.  Lane 0 of each wave
+// stores the wave's sum in slots[par][wave]; after one barrier every thread
+// adds the W slots in index order (the same order in every thread, so all
+// hold the same value).  Successive calls alternate between the two slot
+// arrays: the stores of a call can only meet the reads of the call before
+// the previous one, and those completed before the previous call's barrier.
 template <int NT>
-__device__ __forceinline__ double block_sum_all(double v, double* red, double* bcast) {
-  const double t = block_sum<NT>(v, red);
-  if (threadIdx.x == 0) *bcast = t;
-  __syncthreads();
-  const double r = *bcast;
-  __syncthreads();  // red and bcast are reused
-  return r;
+__device__ __forceinline__ double block_allsum(double v, double (*slots)[NT / 64], int& par) {
+  constexpr int W = NT / 64;
+  v = wave_sum(v);
+  if constexpr (W == 1) {
+    return v;
+  } else {
+    if ((threadIdx.x & 63) == 0) slots[par][threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) s += slots[par][i];
+    par ^= 1;
+    return s;
+  }
 }
 
-template <int N, int ST>
+// q += S^H F^H (M/ny) F (S p) over one coil's maps s (column transforms).
+template <int N, int T, int SY, class View, class Tw, class Rad>
+__device__ __forceinline__ void coil_term(const c32* s, const c32* p, c32* q, const float* mu, int t, const Tw& tw,
+                                          View lv, Rad) {
+  constexpr int E = N / T;
+  c32 u[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) u[j] = cmul(s[j], p[j]);
+  fft_line<N, T, -1, SY>(u, t, tw, lv, Rad{});
+#pragma unroll
+  for (int j = 0; j < E; ++j) u[j] = cscale(u[j], mu[j]);
+  fft_line<N, T, +1, SY>(u, t, tw, lv, Rad{});
+#pragma unroll
+  for (int j = 0; j < E; ++j) q[j] = cfma_conj(q[j], s[j], u[j]);
+}
+
+template <bool WL>
+struct SmallView;
+template <>
+struct SmallView<true> {
+  using type = PadLineView;
+  template <int LP>
+  __device__ static type make(c32* xbuf, int cx) { return {xbuf + cx * LP}; }
+};
+template <>
+struct SmallView<false> {
+  using type = LineView<kSmallCols>;
+  template <int LP>
+  __device__ static type make(c32* xbuf, int cx) { return {xbuf + cx}; }
+};
+
+template <int N, int ST, bool MREG, bool WL>
 __global__ void __launch_bounds__(Len<N>::T * kSmallCols) cg_small_kernel(SmallParams P) {
   constexpr int T = Len<N>::T;
   constexpr int E = Len<N>::E;
-  constexpr int TX = kSmallCols;
-  constexpr int NT = T * TX;
+  constexpr int NT = T * kSmallCols;
+  constexpr int LP = padded_line<N>();
+  constexpr int CR = MREG ? kSmallRegCoils : 1;
+  static_assert(64 % T == 0, "a column's threads must share one wavefront");
   using Rad = typename Len<N>::R;
   using SType = typename StorageT<ST>::T;
 
-  __shared__ c32 xbuf[N * TX];
+  __shared__ c32 xbuf[kSmallCols * LP];
   __shared__ c32 tw[N];
-  __shared__ float mu[N];
-  __shared__ double red[NT / 64];
-  __shared__ double bcast;
+  __shared__ double slots[2][NT / 64];
 
   const int tid = threadIdx.x;
-  const int cx = tid % TX;
-  const int t = tid / TX;
+  const int t = WL ? tid % T : tid / kSmallCols;   // position in the column's line
+  const int cx = WL ? tid / T : tid % kSmallCols;  // column
+  constexpr int SY = WL ? kSyncWave : kSyncBlock;
   const int b = blockIdx.x;
   const long nx = P.nx;
   const bool valid = cx < nx;
@@ -83,10 +145,10 @@ __global__ void __launch_bounds__(Len<N>::T * kSmallCols) cg_small_kernel(SmallP
   const uint32_t rstep = (uint32_t)T * (uint32_t)nx;
   const uint32_t img_bytes = (uint32_t)(nvox * (long)sizeof(c32));
 
-  for (int i = tid; i < N; i += NT) {
-    tw[i] = P.tw[i];
-    mu[i] = P.mu[i];
-  }
+  for (int i = tid; i < N; i += NT) tw[i] = P.tw[i];
+  float mu[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) mu[j] = P.mu[t + T * j];
 
   c32 x[E], r[E], p[E], q[E];
   double rr = 0.0;
@@ -100,19 +162,31 @@ __global__ void __launch_bounds__(Len<N>::T * kSmallCols) cg_small_kernel(SmallP
       if (valid) rr += (double)r[j].re * (double)r[j].re + (double)r[j].im * (double)r[j].im;
     }
   }
+
+  const SType* S = static_cast<const SType*>(P.maps) + (long)b * P.maps_bstride;
+  const uint32_t coil_bytes = (uint32_t)(nvox * (long)sizeof(SType));
+  c32 sm[CR][E];
+  if constexpr (MREG) {
+#pragma unroll
+    for (int c = 0; c < CR; ++c) {
+      if (c < P.ncoils) {
+        const Buf bs = make_buf(S + (long)c * nvox, coil_bytes);
+#pragma unroll
+        for (int j = 0; j < E; ++j) sm[c][j] = buf_load_st<ST>(bs, voff, (uint32_t)j * rstep);
+      }
+    }
+  }
   __syncthreads();
 
   using TwC = TwChoice<N, T, Rad>;
   typename TwC::type twsrc;
   if constexpr (TwC::regs) twsrc.load(tw, t);
   else twsrc.tw = tw;
-  LineView<TX> lv{&xbuf[cx]};
+  const auto lv = SmallView<WL>::template make<LP>(xbuf, cx);
 
-  const SType* S = static_cast<const SType*>(P.maps) + (long)b * P.maps_bstride;
-  const uint32_t coil_bytes = (uint32_t)(nvox * (long)sizeof(SType));
   double* hist = P.rho_hist ? P.rho_hist + (long)b * P.hist_len : nullptr;
-
-  double rho = block_sum_all<NT>(rr, red, &bcast);
+  int par = 0;
+  double rho = block_allsum<NT>(rr, slots, par);
   const double rho0 = rho;
   if (tid == 0 && hist && P.hist_len > 0) hist[0] = rho;
   int status = finite64(rho) ? CG_RUNNING : CG_NONFINITE;
@@ -125,19 +199,18 @@ __global__ void __launch_bounds__(Len<N>::T * kSmallCols) cg_small_kernel(SmallP
     // q = A p
 #pragma unroll
     for (int j = 0; j < E; ++j) q[j] = {0.f, 0.f};
-    for (int c = 0; c < P.ncoils; ++c) {
-      const Buf bs = make_buf(S + (long)c * nvox, coil_bytes);
-      c32 s[E], u[E];
+    if constexpr (MREG) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) s[j] = buf_load_st<ST>(bs, voff, (uint32_t)j * rstep);
+      for (int c = 0; c < CR; ++c)
+        if (c < P.ncoils) coil_term<N, T, SY>(sm[c], p, q, mu, t, twsrc, lv, Rad{});
+    } else {
+      for (int c = 0; c < P.ncoils; ++c) {
+        const Buf bs = make_buf(S + (long)c * nvox, coil_bytes);
+        c32 s[E];
 #pragma unroll
-      for (int j = 0; j < E; ++j) u[j] = cmul(s[j], p[j]);
-      fft_line<N, T, -1>(u, t, twsrc, lv, Rad{});
-#pragma unroll
-      for (int j = 0; j < E; ++j) u[j] = cscale(u[j], mu[t + T * j]);
-      fft_line<N, T, +1>(u, t, twsrc, lv, Rad{});
-#pragma unroll
-      for (int j = 0; j < E; ++j) q[j] = cfma_conj(q[j], s[j], u[j]);
+        for (int j = 0; j < E; ++j) s[j] = buf_load_st<ST>(bs, voff, (uint32_t)j * rstep);
+        coil_term<N, T, SY>(s, p, q, mu, t, twsrc, lv, Rad{});
+      }
     }
     double pq = 0.0;
 #pragma unroll
@@ -145,7 +218,7 @@ __global__ void __launch_bounds__(Len<N>::T * kSmallCols) cg_small_kernel(SmallP
       q[j] = {q[j].re + P.lambda * p[j].re, q[j].im + P.lambda * p[j].im};
       if (valid) pq += (double)p[j].re * (double)q[j].re + (double)p[j].im * (double)q[j].im;
     }
-    const double eta = block_sum_all<NT>(pq, red, &bcast);
+    const double eta = block_allsum<NT>(pq, slots, par);
     if (!finite64(eta)) {
       status = CG_NONFINITE;
       break;
@@ -162,7 +235,7 @@ __global__ void __launch_bounds__(Len<N>::T * kSmallCols) cg_small_kernel(SmallP
       r[j] = {(float)((double)r[j].re - alpha * q[j].re), (float)((double)r[j].im - alpha * q[j].im)};
       if (valid) rr += (double)r[j].re * (double)r[j].re + (double)r[j].im * (double)r[j].im;
     }
-    const double rho_new = block_sum_all<NT>(rr, red, &bcast);
+    const double rho_new = block_allsum<NT>(rr, slots, par);
     ++k;
     if (tid == 0 && hist && k < P.hist_len) hist[k] = rho_new;
     if (!finite64(rho_new)) {
@@ -213,6 +286,16 @@ bool small_solve_supported(const Geom& g) {
   return ok;
 }
 
+template <int N, int ST>
+static void launch_small_st(const SmallParams& P, int batch, hipStream_t st) {
+  const dim3 grid((unsigned)batch), block(Len<N>::T * kSmallCols);
+  constexpr bool kWaveLines = !(ST == ST_C64 && N == 64);
+  if (Len<N>::E <= 8 && P.ncoils <= kSmallRegCoils)
+    hipLaunchKernelGGL((cg_small_kernel<N, ST, true, true>), grid, block, 0, st, P);
+  else
+    hipLaunchKernelGGL((cg_small_kernel<N, ST, false, kWaveLines>), grid, block, 0, st, P);
+}
+
 hipError_t launch_cg_small(const Geom& g, const Tables& tb, const void* maps, const c32* bvec, c32* x, int K,
                            float lambda, const CgArgs& cg, CgInfo* info, CgInfo* info2, hipStream_t st) {
   if (!small_solve_supported(g)) return hipErrorInvalidValue;
@@ -237,11 +320,10 @@ hipError_t launch_cg_small(const Geom& g, const Tables& tb, const void* maps, co
   dispatch_length(g.ny, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     if constexpr (small_len<N>()) {
-      const dim3 grid((unsigned)g.batch), block(Len<N>::T * kSmallCols);
       switch (g.maps_storage) {
-        case ST_C64: hipLaunchKernelGGL((cg_small_kernel<N, ST_C64>), grid, block, 0, st, P); break;
-        case ST_BF16: hipLaunchKernelGGL((cg_small_kernel<N, ST_BF16>), grid, block, 0, st, P); break;
-        case ST_FP16: hipLaunchKernelGGL((cg_small_kernel<N, ST_FP16>), grid, block, 0, st, P); break;
+        case ST_C64: launch_small_st<N, ST_C64>(P, g.batch, st); break;
+        case ST_BF16: launch_small_st<N, ST_BF16>(P, g.batch, st); break;
+        case ST_FP16: launch_small_st<N, ST_FP16>(P, g.batch, st); break;
         default: return;
       }
       err = hipGetLastError();

@@ -243,6 +243,8 @@ SMALL_CASES = [  # ny, nx, coils, batch, per-slice maps, storage
     (48, 16, 3, 1, False, "c64"),
     (64, 64, 8, 2, False, "bf16"),
     (64, 32, 4, 1, True, "c64"),
+    (64, 48, 6, 2, True, "c64"),   # maps re-read per iteration, block layout
+    (32, 16, 4, 2, False, "fp16"),  # maps held in registers, 16-bit storage
 ]
 
 
