@@ -18,17 +18,22 @@
 // line, so the transform's exchanges need no block barrier and the only
 // block barriers of an iteration are those of the two inner products.
 // Otherwise a wavefront spans 64 columns at one row offset (whole-line map
-// reads) and the exchanges take block barriers.  With at most
-// kSmallRegCoils coils and at most 8 elements per thread the sensitivity
-// maps are read once, before the first iteration, and held in registers
-// (MREG); otherwise each iteration reads them again (from L2).  Measured on
+// reads) and the exchanges take block barriers.  When the slice has at most
+// SmallLen<N>::CR coils the sensitivity maps are read once, before the
+// first iteration, and held in registers (MREG: 32 complex values per
+// thread, 8 coils at 32 rows, where one wave per SIMD leaves room for 64);
+// otherwise each iteration reads them again (from L2).  Measured on
 // MI355X, 20 iterations of one slice: 64^2 with 4 coils 172.8 us with the
 // maps re-read and the block layout, 129.6 us with the maps in registers and
 // wave-local lines, 145.1 us with the maps in registers and the block
 // layout.  Without MREG wave-local lines are faster except for complex64
 // maps at 64 rows (wave-local against block layout: 48^2 x 8 coils, BF16
 // maps, 272 against 319 us; 64^2 x 8 coils, complex64 maps, 333 against
-// 298 us).
+// 298 us).  Maps in registers against re-read, wave-local lines: 16^2 x 8
+// coils 123.8 -> 99.6 us, 32^2 x 8 coils 210.2 -> 185.7 us, 48^2 x 2 coils
+// 120.5 -> 99.6 us.  Four threads per 64-point line (three radix-4 stages,
+// four waves per SIMD) do not leave room for the maps; eight threads per
+// 32-point line (three stages) were slower (109 -> 134 us at 4 coils).
 #include "bufio.hpp"
 #include "kernels.hpp"
 #include "lengths.hpp"
@@ -37,7 +42,6 @@
 namespace sense {
 
 constexpr int kSmallCols = 64;  // columns per workgroup: the whole slice
-constexpr int kSmallRegCoils = 4;
 
 struct SmallParams {
   const void* maps;
@@ -56,6 +60,17 @@ struct SmallParams {
   CgInfo* info2;     // [B] caller copy or null
   double* rho_hist;  // [B][hist_len] or null
   int hist_len;
+};
+
+// The transform configuration of the whole-solve kernel, and CR: the most
+// coils whose maps it holds in registers.
+template <int N>
+struct SmallLen : Len<N> {
+  static constexpr int CR = 32 / Len<N>::E;
+};
+template <>
+struct SmallLen<32> : Len<32> {
+  static constexpr int CR = 8;
 };
 
 template <int N>
@@ -118,14 +133,14 @@ struct SmallView<false> {
 };
 
 template <int N, int ST, bool MREG, bool WL>
-__global__ void __launch_bounds__(Len<N>::T * kSmallCols) cg_small_kernel(SmallParams P) {
-  constexpr int T = Len<N>::T;
-  constexpr int E = Len<N>::E;
+__global__ void __launch_bounds__(SmallLen<N>::T * kSmallCols) cg_small_kernel(SmallParams P) {
+  constexpr int T = SmallLen<N>::T;
+  constexpr int E = SmallLen<N>::E;
   constexpr int NT = T * kSmallCols;
   constexpr int LP = padded_line<N>();
-  constexpr int CR = MREG ? kSmallRegCoils : 1;
+  constexpr int CR = MREG ? SmallLen<N>::CR : 1;
   static_assert(64 % T == 0, "a column's threads must share one wavefront");
-  using Rad = typename Len<N>::R;
+  using Rad = typename SmallLen<N>::R;
   using SType = typename StorageT<ST>::T;
 
   __shared__ c32 xbuf[kSmallCols * LP];
@@ -288,9 +303,9 @@ bool small_solve_supported(const Geom& g) {
 
 template <int N, int ST>
 static void launch_small_st(const SmallParams& P, int batch, hipStream_t st) {
-  const dim3 grid((unsigned)batch), block(Len<N>::T * kSmallCols);
+  const dim3 grid((unsigned)batch), block(SmallLen<N>::T * kSmallCols);
   constexpr bool kWaveLines = !(ST == ST_C64 && N == 64);
-  if (Len<N>::E <= 8 && P.ncoils <= kSmallRegCoils)
+  if (P.ncoils <= SmallLen<N>::CR)
     hipLaunchKernelGGL((cg_small_kernel<N, ST, true, true>), grid, block, 0, st, P);
   else
     hipLaunchKernelGGL((cg_small_kernel<N, ST, false, kWaveLines>), grid, block, 0, st, P);

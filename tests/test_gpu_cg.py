@@ -245,6 +245,8 @@ SMALL_CASES = [  # ny, nx, coils, batch, per-slice maps, storage
     (64, 32, 4, 1, True, "c64"),
     (64, 48, 6, 2, True, "c64"),   # maps re-read per iteration, block layout
     (32, 16, 4, 2, False, "fp16"),  # maps held in registers, 16-bit storage
+    (32, 48, 7, 2, True, "c64"),    # 7 of 8 register coil slots
+    (48, 32, 2, 1, True, "bf16"),   # 48 rows: two coils in registers
 ]
 
 
