@@ -229,8 +229,11 @@ SENSE_API sense_status sense_cg_solve_static(const sense_desc* desc, const void*
  * d_rho_hist) captures every kernel of the solve into a HIP graph on a
  * private stream; later calls with the same arguments replay it on the
  * caller's stream with one launch.  Different arguments re-capture.  While
- * profiling is enabled solves run eagerly.  The maps and mask never change
- * for a plan, so a replay computes exactly what the eager launches do.
+ * profiling is enabled solves run eagerly, and so do the solves of slices
+ * that run whole in one workgroup (at most 64 x 64 with one coil group:
+ * three launches, where a graph launch costs more than it saves).  The
+ * mask never changes for a plan and new maps drop the graph, so a replay
+ * computes exactly what the eager launches do.
  */
 SENSE_API sense_status sense_plan_set_graphs(sense_plan plan, int32_t enable);
 

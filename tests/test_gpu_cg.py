@@ -280,9 +280,9 @@ def test_small_whole_solve_matches_oracle(ny, nx, nc, b, per, st):
 
 
 def test_small_whole_solve_equals_graph_replay_and_engine():
-    """The whole-solve launch replays bitwise from its graph, and a small
-    request in the serving engine (run whole at admission) equals the plain
-    solve bitwise."""
+    """A small solve gives the same bits with graphs on (where it still
+    launches eagerly) and off, and a small request in the serving engine
+    (run whole at admission) equals the plain solve bitwise."""
     w = synth.SMALL_64
     imgs, maps, mask, y = _problem(w)
     with sense.Plan(to_dev(maps), mask) as plan, sense.Plan(to_dev(maps), mask) as pe:
