@@ -127,14 +127,28 @@ def test_cg_batch_per_slice_maps():
     assert list(res.iters) == [12, 12, 12]
 
 
-def test_cg_statuses():
+def _split(plan, split):
+    """With split, force the workspace's largest coil-group count, which
+    takes the per-iteration fused launches instead of the whole-solve
+    kernel of small slices."""
+    if split:
+        gmax = plan.coil_groups()[1]
+        assert gmax > 1
+        plan.set_coil_groups(gmax)
+    return plan
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_cg_statuses(split):
+    """Every stop status, on the whole-solve kernel of small slices and on
+    the per-iteration fused launches."""
     n, nc = 32, 4
     maps = c64(synth.coil_maps2d(n, nc))
     mask = synth.mask_regular(n, 2, 4)
     full = np.ones(n, np.uint8)
     x_true = synth.phantom2d(n, seed=3)[None]
     # zero data: EXACT before the first update
-    with sense.Plan(to_dev(maps), mask) as plan:
+    with _split(sense.Plan(to_dev(maps), mask), split) as plan:
         res = plan.cg(torch.zeros((1, nc, n, n), dtype=torch.complex64, device="cuda:0"), 5)
         assert res.status[0] == sense.EXACT and res.iters[0] == 0
         assert torch.count_nonzero(res.x) == 0
@@ -150,7 +164,7 @@ def test_cg_statuses():
         res = plan.cg(to_dev(yn), 5)
         assert res.status[0] == sense.NONFINITE and res.iters[0] == 0
     # A = 0 (lambda = -1 with full sampling and sum |S|^2 = 1): breakdown
-    with sense.Plan(to_dev(maps), full) as plan:
+    with _split(sense.Plan(to_dev(maps), full), split) as plan:
         y = c64(oracle.E(x_true, maps, full))
         res = plan.cg(to_dev(y), 5, lam=-1.0)
         assert res.status[0] == sense.BREAKDOWN and res.iters[0] == 0
