@@ -32,7 +32,12 @@
  *  - complex64 = two float32; SENSE_BF16X2 / SENSE_FP16X2 = two 16-bit
  *    values (re at the lower address).  x, p, q are always complex64.
  *  - Pointers named d_* are device pointers on the plan's device, owned by
- *    the caller.  Pointers named h_* are host memory.
+ *    the caller.  Pointers named h_* are host memory.  Device buffers of
+ *    maps, images and k-space must be 16-byte aligned (the kernels use
+ *    16-byte vector accesses), d_info and d_rho_hist 8-byte aligned; every
+ *    allocation of the HIP runtime or of torch is, and so is every batch or
+ *    coil slab of one, since each slab of a supported size is a multiple of
+ *    16 bytes.  A misaligned pointer fails with SENSE_ERR_INVALID.
  *  - stream is a hipStream_t passed as void* (NULL = the null stream).
  *    Apply and solve calls are asynchronous: they enqueue work on the
  *    stream and return; results are valid once the stream is synchronised.

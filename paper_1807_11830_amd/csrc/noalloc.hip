@@ -93,6 +93,7 @@ extern "C" sense_status sense_cg_solve_static(const sense_desc* desc, const void
     const sense_desc& d = *desc;
     if (d.ndim != 2) return fail(SENSE_ERR_UNSUPPORTED, "sense_cg_solve_static supports 2D problems only");
     if (!d_maps) return fail(SENSE_ERR_INVALID, "d_maps is NULL");
+    if (check_aligned16({d_maps}, "d_maps") != SENSE_OK) return SENSE_ERR_INVALID;
     if (!h_mask) return fail(SENSE_ERR_INVALID, "h_mask is NULL");
     if (!length_supported(d.nx)) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
     const Layout L = make_layout(d);
@@ -126,6 +127,8 @@ extern "C" sense_status sense_cg_solve_static(const sense_desc* desc, const void
     bind_tables(&p);
 
     s = check_solve_args(&p, d_y, d_x, max_iter, rel_tol, lambda);
+    if (s != SENSE_OK) return s;
+    s = check_info_aligned(d_info, d_rho_hist);
     if (s != SENSE_OK) return s;
 
     hipStream_t st = static_cast<hipStream_t>(stream);

@@ -297,9 +297,28 @@ hipError_t enqueue_solve(sense_plan p, const void* d_y, c32* x, int32_t max_iter
   return e;
 }
 
+namespace sense {
+
+bool aligned_to(const void* p, size_t n) { return reinterpret_cast<uintptr_t>(p) % n == 0; }
+
+sense_status check_aligned16(std::initializer_list<const void*> ps, const char* names) {
+  for (const void* q : ps)
+    if (q && !aligned_to(q, 16)) return fail(SENSE_ERR_INVALID, std::string(names) + " must be 16-byte aligned");
+  return SENSE_OK;
+}
+
+sense_status check_info_aligned(const void* d_info, const void* d_rho_hist) {
+  if ((d_info && !aligned_to(d_info, 8)) || (d_rho_hist && !aligned_to(d_rho_hist, 8)))
+    return fail(SENSE_ERR_INVALID, "d_info and d_rho_hist must be 8-byte aligned");
+  return SENSE_OK;
+}
+
+}  // namespace sense
+
 sense_status check_solve_args(sense_plan p, const void* d_y, void* d_x, int32_t max_iter,
                                      double rel_tol, double lambda) {
   if (!d_x || !d_y) return fail(SENSE_ERR_INVALID, "d_x and d_y must be non-NULL");
+  if (check_aligned16({d_x, d_y}, "d_x and d_y") != SENSE_OK) return SENSE_ERR_INVALID;
   if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
   if (max_iter < 0) return fail(SENSE_ERR_INVALID, "max_iter must be >= 0");
   if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return fail(SENSE_ERR_INVALID, "rel_tol must be finite and >= 0");
@@ -328,6 +347,7 @@ sense_status sense_plan_create(const sense_desc* desc, const void* d_maps, const
     sense_status s = validate_desc(desc);
     if (s != SENSE_OK) return s;
     if (!d_maps) return fail(SENSE_ERR_INVALID, "d_maps is NULL");
+    if (check_aligned16({d_maps}, "d_maps") != SENSE_OK) return SENSE_ERR_INVALID;
     if (!h_mask) return fail(SENSE_ERR_INVALID, "h_mask is NULL");
     const sense_desc& d = *desc;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -404,6 +424,7 @@ sense_status sense_apply_E(sense_plan p, const void* d_x, void* d_y, void* strea
   sense_status s = check_plan(p);
   if (s != SENSE_OK) return s;
   if (!d_x || !d_y) return fail(SENSE_ERR_INVALID, "d_x and d_y must be non-NULL");
+  if (check_aligned16({d_x, d_y}, "d_x and d_y") != SENSE_OK) return SENSE_ERR_INVALID;
   if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
   const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
   const size_t xb = nvox * p->d.batch * sizeof(c32);
@@ -418,6 +439,7 @@ sense_status sense_apply_EH(sense_plan p, const void* d_y, void* d_x, void* stre
   sense_status s = check_plan(p);
   if (s != SENSE_OK) return s;
   if (!d_x || !d_y) return fail(SENSE_ERR_INVALID, "d_x and d_y must be non-NULL");
+  if (check_aligned16({d_x, d_y}, "d_x and d_y") != SENSE_OK) return SENSE_ERR_INVALID;
   if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
   const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
   const size_t xb = nvox * p->d.batch * sizeof(c32);
@@ -432,6 +454,7 @@ sense_status sense_apply_rss(sense_plan p, const void* d_y, float* d_img, void* 
   sense_status s = check_plan(p);
   if (s != SENSE_OK) return s;
   if (!d_y || !d_img) return fail(SENSE_ERR_INVALID, "d_y and d_img must be non-NULL");
+  if (check_aligned16({d_y, d_img}, "d_y and d_img") != SENSE_OK) return SENSE_ERR_INVALID;
   if (!p->full_ops) return fail(SENSE_ERR_UNSUPPORTED, "nx is not a supported transform length");
   const size_t nvox = (size_t)p->d.nx * p->d.ny * p->d.nz;
   const size_t ob = nvox * p->d.batch * sizeof(float);
@@ -446,6 +469,7 @@ sense_status sense_apply_EHE(sense_plan p, const void* d_p, void* d_q, double la
   sense_status s = check_plan(p);
   if (s != SENSE_OK) return s;
   if (!d_p || !d_q) return fail(SENSE_ERR_INVALID, "d_p and d_q must be non-NULL");
+  if (check_aligned16({d_p, d_q}, "d_p and d_q") != SENSE_OK) return SENSE_ERR_INVALID;
   if (!std::isfinite(lambda)) return fail(SENSE_ERR_INVALID, "lambda must be finite");
   const size_t bytes = (size_t)p->d.nx * p->d.ny * p->d.nz * p->d.batch * sizeof(c32);
   if (overlap(d_p, bytes, d_q, bytes)) return fail(SENSE_ERR_INVALID, "d_p and d_q overlap");
@@ -468,6 +492,8 @@ sense_status sense_cg_solve(sense_plan p, const void* d_y, void* d_x, int32_t ma
   sense_status s = check_plan(p);
   if (s != SENSE_OK) return s;
   s = check_solve_args(p, d_y, d_x, max_iter, rel_tol, lambda);
+  if (s != SENSE_OK) return s;
+  s = check_info_aligned(d_info, d_rho_hist);
   if (s != SENSE_OK) return s;
   if (p->busy) return fail(SENSE_ERR_STATE, "plan is in a serving-engine slot");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -515,6 +541,7 @@ sense_status sense_plan_set_maps(sense_plan p, const void* d_maps) {
   sense_status s = check_plan(p);
   if (s != SENSE_OK) return s;
   if (!d_maps) return fail(SENSE_ERR_INVALID, "d_maps is NULL");
+  if (check_aligned16({d_maps}, "d_maps") != SENSE_OK) return SENSE_ERR_INVALID;
   if (p->busy) return fail(SENSE_ERR_STATE, "plan is in a serving-engine slot");
   p->maps = d_maps;
   if (p->gexec) {

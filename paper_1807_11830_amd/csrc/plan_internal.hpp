@@ -2,6 +2,8 @@
 // serving engine (engine.hip).  Not part of the public interface.
 #pragma once
 
+#include <initializer_list>
+
 #include <string>
 #include <utility>
 #include <vector>
@@ -34,6 +36,13 @@ void host_mask_tables(const uint8_t* h_mask, long ny, long nz, uint8_t* mask, fl
                       int32_t* rows_u, int* n_s, int* n_u);
 sense_status device_fail(hipError_t e, const char* what);
 bool overlap(const void* a, size_t na, const void* b, size_t nb);
+// Whether p is a multiple of n bytes (kernels access the caller's buffers
+// with 16-byte vector instructions and the CG info with 8-byte stores).
+bool aligned_to(const void* p, size_t n);
+// Fails unless every non-NULL pointer in ps is 16-byte aligned.
+sense_status check_aligned16(std::initializer_list<const void*> ps, const char* names);
+// Fails unless d_info and d_rho_hist (either may be NULL) are 8-byte aligned.
+sense_status check_info_aligned(const void* d_info, const void* d_rho_hist);
 size_t storage_bytes(int st);
 
 }  // namespace sense

@@ -95,14 +95,15 @@ def test_null_arguments():
     L = sense.lib()
     h = ctypes.c_void_p()
     mask = (ctypes.c_uint8 * 64)()
-    assert L.sense_plan_create(None, ctypes.c_void_p(1), ctypes.cast(mask, ctypes.c_void_p), None,
+    assert L.sense_plan_create(None, ctypes.c_void_p(256), ctypes.cast(mask, ctypes.c_void_p), None,
                                ctypes.byref(h)) == 1
     assert L.sense_plan_create(ctypes.byref(_desc()), None, ctypes.cast(mask, ctypes.c_void_p), None,
                                ctypes.byref(h)) == 1
     assert "d_maps" in L.sense_last_error().decode()
-    assert L.sense_plan_create(ctypes.byref(_desc()), ctypes.c_void_p(1), None, None,
+    assert L.sense_plan_create(ctypes.byref(_desc()), ctypes.c_void_p(256), None, None,
                                ctypes.byref(h)) == 1
-    assert L.sense_plan_create(ctypes.byref(_desc()), ctypes.c_void_p(1),
+    assert "h_mask" in L.sense_last_error().decode()
+    assert L.sense_plan_create(ctypes.byref(_desc()), ctypes.c_void_p(256),
                                ctypes.cast(mask, ctypes.c_void_p), None, None) == 1
     for f, args in (("sense_apply_E", (None, None, None, None)),
                     ("sense_apply_EH", (None, None, None, None)),
@@ -115,6 +116,22 @@ def test_null_arguments():
                     ("sense_plan_coil_groups", (None, None, None))):
         assert getattr(L, f)(*args) == 1, f
         assert "plan is NULL" in L.sense_last_error().decode()
+
+
+def test_misaligned_maps_rejected():
+    """Device buffers must be 16-byte aligned; the maps pointer is checked
+    before any device call, so this runs without a GPU."""
+    L = sense.lib()
+    h = ctypes.c_void_p()
+    mask = (ctypes.c_uint8 * 64)(*([1] * 64))
+    assert L.sense_plan_create(ctypes.byref(_desc()), ctypes.c_void_p(256 + 8),
+                               ctypes.cast(mask, ctypes.c_void_p), None, ctypes.byref(h)) == 1
+    assert "d_maps must be 16-byte aligned" in L.sense_last_error().decode()
+    assert not h.value
+    assert L.sense_cg_solve_static(ctypes.byref(_desc()), ctypes.c_void_p(256 + 4),
+                                   ctypes.cast(mask, ctypes.c_void_p), ctypes.c_void_p(512),
+                                   ctypes.c_void_p(1024), 5, 0.0, 0.0, None, None, None) == 1
+    assert "d_maps must be 16-byte aligned" in L.sense_last_error().decode()
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -6,6 +6,8 @@ tolerance of the stated fp32 path); shapes span several column tiles and a
 ragged last tile, every compiled transform length, shared and per-batch
 maps, and lambda != 0.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -267,6 +269,22 @@ def test_invalid_calls_on_gpu():
             sense._check(sense.lib().sense_apply_EHE(plan._h, sense._ptr(p), sense._ptr(p), 0.0, None))
         with pytest.raises(sense.SenseError):
             plan.EHE(p.to(torch.complex128))
+        # one complex64 element into a buffer is 8-byte aligned only: every
+        # device buffer must be 16-byte aligned (nothing is enqueued)
+        big = torch.zeros(2 * p.numel() + 2, dtype=torch.complex64, device="cuda:0")
+        off = ctypes.c_void_p(big.data_ptr() + 8)
+        L = sense.lib()
+        for call in (lambda: L.sense_apply_EHE(plan._h, sense._ptr(p), off, 0.0, None),
+                     lambda: L.sense_apply_EH(plan._h, off, sense._ptr(p), None),
+                     lambda: L.sense_cg_solve(plan._h, sense._ptr(big), off, 3, 0.0, 0.0, None, None, None)):
+            with pytest.raises(sense.SenseError, match="16-byte aligned"):
+                sense._check(call())
+        info = torch.zeros(8, dtype=torch.float64, device="cuda:0")
+        with pytest.raises(sense.SenseError, match="8-byte aligned"):
+            sense._check(L.sense_cg_solve(plan._h, sense._ptr(big), sense._ptr(p), 3, 0.0, 0.0,
+                                          ctypes.c_void_p(info.data_ptr() + 4), None, None))
+        torch.cuda.synchronize()
+        assert torch.count_nonzero(big) == 0
     with pytest.raises(sense.SenseError, match="unsupported|ny=100"):
         sense.Plan(to_dev(0.5 * synth.complex_normal((2, 100, 64), 1)), np.ones(100, np.uint8))
 
