@@ -313,7 +313,9 @@ SENSE_API sense_status sense_engine_destroy(sense_engine engine);
  * waits for everything enqueued there before this admission, so the solve
  * never reads k-space that is still being written.  The wait covers only
  * work enqueued before the call.  Results are in d_x once poll reports the
- * slot; the caller may then read them on any stream.
+ * slot; the caller may then read them on any stream.  d_y and d_x must stay
+ * allocated (and must not be reused) until then, or until the engine is
+ * destroyed, which waits for its streams.
  */
 SENSE_API sense_status sense_engine_admit(sense_engine engine, sense_plan plan, const void* d_y, void* d_x,
                                           int32_t max_iter, double rel_tol, double lambda,

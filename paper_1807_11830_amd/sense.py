@@ -432,6 +432,10 @@ class Engine:
             _check(lib().sense_engine_create(int(budget_bytes), self.max_slots, ctypes.byref(h)))
         self._h = h
         self._done = (ctypes.c_int32 * self.max_slots)()
+        # plan, y and x of every admitted slot, held until poll reports it:
+        # the engine's streams read and write them, and torch's allocator
+        # must not hand their memory to another tensor before then
+        self._held = {}
 
     def admit(self, plan: Plan, y: torch.Tensor, x: torch.Tensor, max_iter: int, tol: float = 0.0,
               lam: float = 0.0, footprint: int = 0, stream=None):
@@ -450,6 +454,7 @@ class Engine:
             if "no free slot" in msg or "budget" in msg:
                 return None
         _check(rc)
+        self._held[int(slot.value)] = (plan, y, x)
         return int(slot.value)
 
     def step(self) -> int:
@@ -462,7 +467,10 @@ class Engine:
         n = ctypes.c_int32(0)
         with torch.cuda.device(self.device):
             _check(lib().sense_engine_poll(self._h, self._done, self.max_slots, ctypes.byref(n)))
-        return [int(self._done[i]) for i in range(n.value)]
+        done = [int(self._done[i]) for i in range(n.value)]
+        for slot in done:
+            self._held.pop(slot, None)
+        return done
 
     def stats(self):
         used, budget = ctypes.c_size_t(0), ctypes.c_size_t(0)
@@ -478,8 +486,9 @@ class Engine:
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             with torch.cuda.device(self.device):
-                _check(lib().sense_engine_destroy(self._h))
+                _check(lib().sense_engine_destroy(self._h))  # waits for the engine's streams
             self._h = ctypes.c_void_p()
+            self._held.clear()
 
     def __del__(self):
         try:

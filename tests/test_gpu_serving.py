@@ -206,3 +206,40 @@ def test_admit_waits_for_the_callers_stream():
             eng.sync()
         torch.cuda.synchronize()
     assert torch.equal(x, ref)
+
+
+def test_engine_holds_inputs_until_polled():
+    """The caller may drop a request's k-space right after admission: the
+    engine binding holds it (with the plan and x) until poll reports the
+    slot, so torch's allocator cannot hand that memory to a tensor written
+    meanwhile on the caller's stream.  The result is bitwise the plain
+    solve's."""
+    bank = InputBank()
+    r = Request(0, 0.0, 256, 16, 3, 8)
+    bank.prepare([r])
+    maps, mask = bank.coil_maps(256, 16), bank.mask(256, 3)
+    img = torch.from_numpy(np.stack([bank.synth.phantom2d(256, seed=6)]).astype(np.complex64)).to("cuda:0")
+    with sense.Plan(maps, mask) as pe, sense.Plan(maps, mask) as pref:
+        yref = pref.E(img)
+        ref = pref.cg(yref, 8).x.clone()
+        torch.cuda.synchronize()
+        x = torch.empty((1, 256, 256), dtype=torch.complex64, device="cuda:0")
+        s = torch.cuda.Stream()
+        with sense.Engine(budget_bytes=1 << 32, max_slots=2) as eng:
+            with torch.cuda.stream(s):
+                busy = torch.randn((4096, 4096), device="cuda:0")
+                for _ in range(8):
+                    busy = busy @ busy * 1e-3  # keep the caller's stream busy
+                # the clone's only reference after this line is the engine's
+                assert eng.admit(pe, yref.clone(), x, 8) == 0
+                junk = [torch.full_like(yref, 1e3) for _ in range(4)]
+            assert len(eng._held) == 1
+            done = []
+            while not done:
+                eng.step()
+                done = eng.poll()
+            assert done == [0] and eng._held == {}
+            eng.sync()
+        torch.cuda.synchronize()
+        del junk
+    assert torch.equal(x, ref)
