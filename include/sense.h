@@ -41,7 +41,10 @@
  *  - stream is a hipStream_t passed as void* (NULL = the null stream).
  *    Apply and solve calls are asynchronous: they enqueue work on the
  *    stream and return; results are valid once the stream is synchronised.
- *    They never allocate memory.
+ *    They never allocate memory.  The calls of one plan share its
+ *    workspace: calls of one plan on different streams must be ordered by
+ *    the caller (events or synchronisation), or they race.  Different plans
+ *    are independent.
  *  - Errors: every call returns a sense_status; on failure nothing is
  *    enqueued and sense_last_error() returns a message for the calling
  *    thread.  No C++ exception crosses this boundary.
