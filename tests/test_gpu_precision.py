@@ -107,3 +107,35 @@ def test_precision_batch_16bit(batch_run, b, st):
         f"(bar {K_FLOOR * floor:.3e}), vs GPU complex64 {e_gpu:.3e}")
     assert e_total <= 1e-2
     assert e_arith <= K_FLOOR * floor
+
+
+def test_precision_48_slices_streaming_launch(batch_run):
+    """The 48-slice launch the precision benchmark also times (one coil
+    group, the streaming instantiation of the fused kernel): the 8-slice
+    inputs six times over, so slices 0 and 40 carry slice 0's inputs and
+    are held to slice 0's oracle results (no further oracle runs), and to
+    each other bitwise (the arithmetic of a slice does not depend on its
+    position in the batch)."""
+    maps, mask, y, out = batch_run
+    rep = 6
+    B = rep * maps.shape[0]
+    maps48 = np.concatenate([maps] * rep)
+    y48 = np.concatenate([y] * rep)
+    K = synth.PREC_384.iters
+    xo = _oracle("fp64", 0, maps, mask, y)
+    floor = rel_l2(_oracle("floor", 0, maps, mask, y), xo)
+    for st in ("c64", "bf16"):
+        log(f"precision batch: {st} solve of {B} slices, {K} iterations")
+        with sense.Plan(to_dev(maps48), mask, batch=B, maps_storage=st, kspace_storage=st) as plan:
+            assert plan.coil_groups()[0] == 1
+            res = plan.cg(sense.to_storage(to_dev(y48), st), K)
+            assert list(res.iters) == [K] * B
+            x = to_host(res.x)
+        assert np.array_equal(x[0], x[40])
+        ref = xo if st == "c64" else _oracle("quantised", 0, maps, mask, y, st)
+        err = rel_l2(x[0:1], ref)
+        log(f"48 slices, slice 0 {st}: vs oracle{'' if st == 'c64' else ' on quantised inputs'} {err:.3e} "
+            f"(bar {K_FLOOR * floor:.3e})")
+        assert err <= K_FLOOR * floor
+        if st != "c64":
+            assert rel_l2(x[0:1], xo) <= 1e-2
