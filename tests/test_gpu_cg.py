@@ -220,6 +220,40 @@ def test_cg_full_size_batch_sampled():
         assert err <= K_FLOOR * floor
 
 
+def test_cg_full_size_batch_bf16_maps():
+    """The benchmark's launch with BF16 maps (`--maps-storage bf16`: the
+    streaming instantiation with the maps staged through LDS): sampled
+    slices against the oracle on the same quantised maps (K_FLOOR times the
+    complex64 floor) and on the unquantised ones (the 1e-2 bar)."""
+    from gpu_common import quantise
+    w = synth.SLICE_256
+    B = 160
+    imgs, maps, mask = synth.slice_inputs(w, B, per_slice_maps=True)
+    maps = c64(maps)
+    picks = [0, 159]
+    y = 0.05 * synth.complex_normal((B, w.ncoils, w.n, w.n), 998) * mask[None, None, :, None]
+    for b in picks:
+        yb = oracle.E(imgs[b:b + 1], maps[b], mask)
+        y[b] = (yb + synth.complex_noise(yb.shape, seed=1000 + b) * mask[None, None, :, None])[0]
+    y = c64(y)
+    with sense.Plan(to_dev(maps), mask, batch=B, maps_storage="bf16") as plan:
+        assert plan.coil_groups()[0] == 1
+        res = plan.cg(to_dev(y), w.iters)
+        torch.cuda.synchronize()
+    assert list(np.unique(res.iters)) == [w.iters]
+    xg = to_host(res.x)
+    for b in picks:
+        mq = quantise(maps[b], "bf16")
+        xq, _, _, _ = oracle.cg(y[b:b + 1], mq, mask, w.iters)
+        floor = rel_l2(oracle.cg(y[b:b + 1], mq, mask, w.iters, vec32=True)[0], xq)
+        xo, _, _, _ = oracle.cg(y[b:b + 1], maps[b], mask, w.iters)
+        e_arith, e_total = rel_l2(xg[b:b + 1], xq), rel_l2(xg[b:b + 1], xo)
+        log(f"slice {b} bf16 maps: vs oracle on quantised maps {e_arith:.3e} (bar {K_FLOOR * floor:.3e}), "
+            f"vs oracle {e_total:.3e}")
+        assert e_arith <= K_FLOOR * floor
+        assert e_total <= 1e-2
+
+
 def test_cg_graph_replay_matches_eager():
     """Whole-solve graph replays, interleaved with eager work and
     synchronisations, reproduce the eager solve bitwise every time; changed
