@@ -213,3 +213,37 @@ def test_3d_full_transform_lengths_match_oracle():
     log(f"  CG (4 iterations) rel-L2 {err:.3e}")
     assert err <= TOL_FP32 and res.iters[0] == 4
     assert np.allclose(res.rho_hist.cpu().numpy()[0], hist[0], rtol=1e-5)
+
+
+def test_3d_full_size_sampled_coil_and_composition():
+    """The 3D workload at its full size (256 x 256 x 128, 16 coils, (ky, kz)
+    mask R = 6 with a 32 x 32 centre: the launches the autograd benchmark
+    times).  Sampled outputs against the oracle: coil 0 of E x (the oracle's
+    forward model with that coil's map alone) and E^H of k-space that is
+    zero outside coil 0.  The normal operator against E^H(E p) and the
+    adjoint identity, on the GPU: properties that hold at any size."""
+    nx, ny, nz, nc = 256, 256, 128, 16
+    maps = c64(synth.coil_maps3d(nx, ny, nz, nc))
+    mask = synth.mask_variable_density_2d(ny, nz, 6.0, (32, 32))
+    xt = c64(synth.phantom3d(nx, ny, nz)[None])
+    y0 = np.zeros((1, nc, nz, ny, nx), np.complex64)
+    y0[:, 0] = c64(synth.complex_normal((1, nz, ny, nx), 61))
+    log(f"3D full size {nx}x{ny}x{nz}, C={nc}")
+    with sense.Plan(to_dev(maps), mask) as plan:
+        xd = to_dev(xt)
+        yd = plan.E(xd)
+        ye = to_host(yd[:, 0:1])
+        xh = to_host(plan.EH(to_dev(y0)))
+        q = plan.EHE(xd)
+        qc = plan.EH(yd)
+        yr = to_dev(c64(synth.complex_normal((1, nc, nz, ny, nx), 62)))
+        lhs = torch.vdot(yd.flatten().to(torch.complex128), yr.flatten().to(torch.complex128))
+        rhs = torch.vdot(xd.flatten().to(torch.complex128), plan.EH(yr).flatten().to(torch.complex128))
+        e_comp = (torch.linalg.vector_norm(q - qc) / torch.linalg.vector_norm(qc)).item()
+        e_adj = (abs(lhs - rhs) / (torch.linalg.vector_norm(yd) * torch.linalg.vector_norm(yr))).item()
+        del yd, q, qc, yr
+    e1 = rel_l2(ye, oracle.E(xt, maps[0:1], mask, ndim=3))
+    e2 = rel_l2(xh, oracle.EH(y0[:, 0:1], maps[0:1], mask, ndim=3))
+    log(f"  E coil 0 {e1:.3e}, EH coil 0 {e2:.3e}, EHE vs EH(E) {e_comp:.3e}, adjoint {e_adj:.3e}")
+    assert max(e1, e2, e_comp) <= TOL_FP32
+    assert e_adj <= 1e-6
