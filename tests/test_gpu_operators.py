@@ -132,10 +132,11 @@ def test_rss_matches_oracle(ny, nx, nc, b, full):
 
 
 @pytest.mark.parametrize("storage", ["c64", "bf16"])
-def test_compact_kspace_equals_full_grid(storage):
+@pytest.mark.parametrize("ny,nx,nc,b", [(128, 96, 4, 2), (64, 48, 3, 2)])
+def test_compact_kspace_equals_full_grid(storage, ny, nx, nc, b):
     """Compact k-space (sampled lines only) gives bitwise the values of the
-    full-grid path on the sampled lines: E, E^H, RSS and CG."""
-    ny, nx, nc, b = 128, 96, 4, 2
+    full-grid path on the sampled lines: E, E^H, RSS and CG (per-iteration
+    launches at 128 x 96, the whole-solve kernel of small slices at 64 x 48)."""
     maps, x, mask = rand_case(ny, nx, nc, b, True, seed=31)
     rows = np.flatnonzero(mask)
     with sense.Plan(to_dev(maps), mask, batch=b, kspace_storage=storage) as pf, \
