@@ -127,6 +127,35 @@ def test_cg_batch_per_slice_maps():
     assert list(res.iters) == [12, 12, 12]
 
 
+@pytest.mark.parametrize("split", [False, True])
+def test_cg_batch_mixed_stops(split):
+    """A batch whose slices stop at different iterations and for different
+    reasons (a tolerance reached at each slice's own iteration, zero data:
+    EXACT before the first update), on the whole-solve kernel of small
+    slices and on the per-iteration fused launches: per-slice iteration
+    counts, statuses and iterates against the oracle."""
+    w = synth.SMALL_64
+    imgs, maps, mask, y = _problem(w, batch=3, per_slice_maps=True)
+    y = y.copy()
+    y[1] = 0
+    y[2] *= 1e-3  # scaling leaves the relative tolerance's stop unchanged
+    y[2] += c64(1e-4 * synth.complex_normal(y[2].shape, 71)) * mask[None, :, None]
+    K, tol = 40, 2e-3  # stops at 5 and 8 iterations, 13-22% clear of tol on either side
+    xo, ito, sto, _ = oracle.cg(y, maps, mask, K, tol=tol)
+    assert sto[1] == oracle.EXACT and ito[1] == 0
+    assert len({int(i) for i in ito}) == 3  # three different stop iterations
+    with _split(sense.Plan(to_dev(maps), mask, batch=3), split) as plan:
+        res = plan.cg(to_dev(y), K, tol=tol)
+    log(f"mixed stops (split={split}): oracle iters {list(ito)} status {list(sto)}, "
+        f"GPU {list(res.iters)} {list(res.status)}")
+    assert list(res.iters) == [int(i) for i in ito]
+    assert list(res.status) == [int(v) for v in sto]
+    xg = to_host(res.x)
+    assert np.count_nonzero(xg[1]) == 0
+    for b in (0, 2):
+        assert rel_l2(xg[b:b + 1], xo[b:b + 1]) <= TOL_FP32
+
+
 def _split(plan, split):
     """With split, force the workspace's largest coil-group count, which
     takes the per-iteration fused launches instead of the whole-solve
