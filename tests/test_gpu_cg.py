@@ -138,7 +138,7 @@ def test_cg_batch_mixed_stops(split):
     imgs, maps, mask, y = _problem(w, batch=3, per_slice_maps=True)
     y = y.copy()
     y[1] = 0
-    # slice 2: scaled data with 10% noise, which converges more slowly
+    # slice 2: scaled-down data plus noise, which converges more slowly
     y[2] *= 1e-3
     y[2] += c64(1e-4 * synth.complex_normal(y[2].shape, 71)) * mask[None, :, None]
     K, tol = 40, 2e-3  # stops at 5 and 8 iterations, 13-22% clear of tol on either side
