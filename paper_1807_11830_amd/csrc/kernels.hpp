@@ -224,11 +224,21 @@ hipError_t launch_combine(const EheParams& P, int batch, bool cg, hipStream_t st
 
 
 // Whole CG solves of small 2D slices (nx <= 64, ny in {8, 16, 32, 48, 64},
-// one coil group): one workgroup per batch element runs all K iterations
-// from b = E^H y and writes x, the CG state, the info and the rho history.
+// one coil group): one workgroup per batch element finishes b = E^H y from
+// the x rows in work (launch_EH_rows: the column transforms and the
+// conjugate coil sum, in the arithmetic of the E^H column pass), runs all K
+// iterations and writes x, the CG state, the info and the rho history.
 bool small_solve_supported(const Geom& g);
-hipError_t launch_cg_small(const Geom& g, const Tables& tb, const void* maps, const c32* bvec, c32* x, int K,
+hipError_t launch_cg_small(const Geom& g, const Tables& tb, const void* maps, const c32* work, c32* x, int K,
                            float lambda, const CgArgs& cg, CgInfo* info, CgInfo* info2, hipStream_t st);
+
+// The x rows of E^H: inverse readout transforms of the sampled k-space
+// lines into work ([B][C][Nz][Ny][Nx] complex64; rows of unsampled lines are
+// not written), unscaled.  adjoint_scale is the factor the column pass of
+// E^H applies after its inverse transforms (unitary scale and centring sign
+// of every axis).
+hipError_t launch_EH_rows(const Geom& g, const Tables& tb, const void* y, c32* work, hipStream_t st);
+float adjoint_scale(const Geom& g);
 
 // Full-grid forward and adjoint operators (2D).
 hipError_t launch_E(const Geom& g, const Tables& tb, const void* maps, const c32* x, c32* work,

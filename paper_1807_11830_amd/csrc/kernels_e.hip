@@ -604,14 +604,20 @@ static hipError_t launch_EH_tail(const Geom& g, const Tables& tb, const void* ma
   return launch_combine(C, g.batch, false, st);
 }
 
+hipError_t launch_EH_rows(const Geom& g, const Tables& tb, const void* y, c32* work, hipStream_t st) {
+  switch (g.kspace_storage) {
+    case ST_C64: return launch_rows<+1, ST_C64, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st);
+    case ST_BF16: return launch_rows<+1, ST_BF16, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st);
+    case ST_FP16: return launch_rows<+1, ST_FP16, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+float adjoint_scale(const Geom& g) { return (float)(axis_scale(g.nx) * axis_scale(g.ny) * axis_scale(g.nz)); }
+
 hipError_t launch_EH(const Geom& g, const Tables& tb, const void* maps, const void* y, c32* work,
                      c32* x, c32* part, int ngroups, hipStream_t st) {
-  hipError_t err = hipErrorInvalidValue;
-  switch (g.kspace_storage) {
-    case ST_C64: err = launch_rows<+1, ST_C64, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st); break;
-    case ST_BF16: err = launch_rows<+1, ST_BF16, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st); break;
-    case ST_FP16: err = launch_rows<+1, ST_FP16, ST_C64>(g, tb.tw_x, y, work, tb.rows_s, tb.n_rows_s, 1.f, st); break;
-  }
+  const hipError_t err = launch_EH_rows(g, tb, y, work, st);
   if (err != hipSuccess) return err;
   return launch_EH_tail(g, tb, maps, work, x, nullptr, 0.f, nullptr, part, ngroups, st);
 }

@@ -10,8 +10,11 @@
 // inner products are block reductions in fp64 with a fixed order, so the
 // result is deterministic; no wait ever spans two workgroups.  One launch
 // replaces the per-iteration launches whose latency dominates a small
-// solve.  The launch after E^H y (which has written b into r) is the whole
-// solve, including the per-problem info.
+// solve.  The launch after the x rows of E^H y is the whole solve: it first
+// finishes b = E^H y (per coil: masked column loads of the rows' output,
+// inverse transform along y, conjugate-sensitivity sum; the arithmetic of
+// the E^H column pass, so b is bitwise the one E^H gives), then iterates,
+// and writes the per-problem info.
 //
 // Two thread layouts.  With wave-local lines (WL) the T threads of a column
 // are consecutive lanes of one wavefront and every column has its own LDS
@@ -45,7 +48,9 @@ constexpr int kSmallCols = 64;  // columns per workgroup: the whole slice
 
 struct SmallParams {
   const void* maps;
-  const c32* b;      // E^H y [B][ny][nx]
+  const c32* w;      // x rows of E^H y [B][C][ny][nx] (unsampled lines unwritten)
+  const uint8_t* mask_c;  // [ny] centred mask
+  float scale;       // unitary scale and centring sign of E^H
   c32* x;            // [B][ny][nx]
   const c32* tw;     // [ny]
   const float* mu;   // [ny] uncentred mask / ny
@@ -162,20 +167,11 @@ __global__ void __launch_bounds__(SmallLen<N>::T * kSmallCols) cg_small_kernel(S
 
   for (int i = tid; i < N; i += NT) tw[i] = P.tw[i];
   float mu[E];
+  bool sampled[E];
 #pragma unroll
-  for (int j = 0; j < E; ++j) mu[j] = P.mu[t + T * j];
-
-  c32 x[E], r[E], p[E], q[E];
-  double rr = 0.0;
-  {
-    const Buf bb = make_buf(P.b + (long)b * nvox, img_bytes);
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      r[j] = buf_load_c64(bb, voff * 8u, (uint32_t)j * rstep * 8u);
-      p[j] = r[j];
-      x[j] = {0.f, 0.f};
-      if (valid) rr += (double)r[j].re * (double)r[j].re + (double)r[j].im * (double)r[j].im;
-    }
+  for (int j = 0; j < E; ++j) {
+    mu[j] = P.mu[t + T * j];
+    sampled[j] = P.mask_c[t + T * j] != 0;
   }
 
   const SType* S = static_cast<const SType*>(P.maps) + (long)b * P.maps_bstride;
@@ -198,6 +194,49 @@ __global__ void __launch_bounds__(SmallLen<N>::T * kSmallCols) cg_small_kernel(S
   if constexpr (TwC::regs) twsrc.load(tw, t);
   else twsrc.tw = tw;
   const auto lv = SmallView<WL>::template make<LP>(xbuf, cx);
+
+  // b = E^H y from the x rows: per coil the checkerboard-signed masked
+  // column (unsampled lines read nothing), inverse transform along y,
+  // conj(S) times the signed result summed over the coils, then the scale
+  c32 x[E], r[E], p[E], q[E];
+  {
+    const float sgn = (t & 1) ? -1.f : 1.f;
+    c32 acc[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) acc[j] = {0.f, 0.f};
+    auto adj_coil = [&](int c, const c32* s) {
+      const Buf bw = make_buf(P.w + ((long)b * P.ncoils + c) * nvox, img_bytes);
+      c32 u[E];
+#pragma unroll
+      for (int j = 0; j < E; ++j)
+        u[j] = cscale(buf_load_c64(bw, sampled[j] ? (voff + (uint32_t)j * rstep) * 8u : kBufOOB, 0), sgn);
+      fft_line<N, T, +1, SY>(u, t, twsrc, lv, Rad{});
+#pragma unroll
+      for (int j = 0; j < E; ++j) acc[j] = cfma_conj(acc[j], s[j], cscale(u[j], sgn));
+    };
+    if constexpr (MREG) {
+#pragma unroll
+      for (int c = 0; c < CR; ++c)
+        if (c < P.ncoils) adj_coil(c, sm[c]);
+    } else {
+      for (int c = 0; c < P.ncoils; ++c) {
+        const Buf bs = make_buf(S + (long)c * nvox, coil_bytes);
+        c32 s[E];
+#pragma unroll
+        for (int j = 0; j < E; ++j) s[j] = buf_load_st<ST>(bs, voff, (uint32_t)j * rstep);
+        adj_coil(c, s);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) r[j] = cscale(acc[j], P.scale);
+  }
+  double rr = 0.0;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    p[j] = r[j];
+    x[j] = {0.f, 0.f};
+    if (valid) rr += (double)r[j].re * (double)r[j].re + (double)r[j].im * (double)r[j].im;
+  }
 
   double* hist = P.rho_hist ? P.rho_hist + (long)b * P.hist_len : nullptr;
   int par = 0;
@@ -311,12 +350,14 @@ static void launch_small_st(const SmallParams& P, int batch, hipStream_t st) {
     hipLaunchKernelGGL((cg_small_kernel<N, ST, false, kWaveLines>), grid, block, 0, st, P);
 }
 
-hipError_t launch_cg_small(const Geom& g, const Tables& tb, const void* maps, const c32* bvec, c32* x, int K,
+hipError_t launch_cg_small(const Geom& g, const Tables& tb, const void* maps, const c32* work, c32* x, int K,
                            float lambda, const CgArgs& cg, CgInfo* info, CgInfo* info2, hipStream_t st) {
   if (!small_solve_supported(g)) return hipErrorInvalidValue;
   SmallParams P{};
   P.maps = maps;
-  P.b = bvec;
+  P.w = work;
+  P.mask_c = tb.mask_c;
+  P.scale = adjoint_scale(g);
   P.x = x;
   P.tw = tb.tw_y;
   P.mu = tb.mu_y;

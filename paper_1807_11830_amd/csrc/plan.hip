@@ -275,15 +275,16 @@ hipError_t enqueue_solve_end(sense_plan p, c32* x, int K, const CgArgs& cg, CgIn
 
 bool small_solve(const sense_plan_s* p) { return p->d.ndim == 2 && p->ngroups == 1 && small_solve_supported(p->g); }
 
-// Small slices: E^H y into r, then one launch runs the whole solve.
+// Small slices: the x rows of E^H y, then one launch finishes E^H y and
+// runs the whole solve.
 hipError_t enqueue_small_solve(sense_plan p, const void* d_y, c32* x, int32_t max_iter, float lambda,
                                const CgArgs& cg, CgInfo* d_info, hipStream_t st) {
-  c32* r = p->at<c32>(p->L.r);
-  hipError_t e = launch_EH(p->g, p->tb, p->maps, d_y, p->at<c32>(p->L.work), r, p->qpart(), p->adj_groups, st);
+  c32* work = p->at<c32>(p->L.work);
+  hipError_t e = launch_EH_rows(p->g, p->tb, d_y, work, st);
   hipEvent_t stop = nullptr;
   if (e == hipSuccess && timed_ehe_begin(p, st, &stop) != SENSE_OK) e = hipErrorUnknown;
   if (e == hipSuccess)
-    e = launch_cg_small(p->g, p->tb, p->maps, r, x, max_iter, lambda, cg, p->at<CgInfo>(p->L.info), d_info, st);
+    e = launch_cg_small(p->g, p->tb, p->maps, work, x, max_iter, lambda, cg, p->at<CgInfo>(p->L.info), d_info, st);
   if (stop && e == hipSuccess) e = hipEventRecord(stop, st);
   return e;
 }
