@@ -429,10 +429,11 @@ def run_precision(args):
 
 def run_small(args):
     """One 64x64 slice, 4 coils, 20 CG iterations: the latency of a single
-    solve as the plan runs it by default (three eager launches: E^H y, then
-    the whole loop in one workgroup), with graphs switched off (the same
-    launches), and with the coils forced into the workspace's fill split
-    (one fused launch per iteration, replayed from the solve's HIP graph)."""
+    solve as the plan runs it by default (two eager launches: the x rows of
+    E^H y, then the rest of E^H y and the whole loop in one workgroup), with
+    graphs switched off (the same launches), and with the coils forced into
+    the workspace's fill split (one fused launch per iteration, replayed
+    from the solve's HIP graph)."""
     import torch
 
     from paper_1807_11830_amd import sense, synth

@@ -239,7 +239,7 @@ SENSE_API sense_status sense_cg_solve_static(const sense_desc* desc, const void*
  * caller's stream with one launch.  Different arguments re-capture.  While
  * profiling is enabled solves run eagerly, and so do the solves of slices
  * that run whole in one workgroup (at most 64 x 64 with one coil group:
- * three launches, where a graph launch costs more than it saves).  The
+ * two launches, where a graph launch costs more than it saves).  The
  * mask never changes for a plan and new maps drop the graph, so a replay
  * computes exactly what the eager launches do.
  */

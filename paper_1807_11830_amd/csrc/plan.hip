@@ -502,9 +502,10 @@ sense_status sense_cg_solve(sense_plan p, const void* d_y, void* d_x, int32_t ma
   CgInfo* info2 = reinterpret_cast<CgInfo*>(d_info);
   const CgArgs cg = p->cg_args(rel_tol, d_rho_hist, d_rho_hist ? max_iter + 1 : 0);
 
-  // A small slice's solve is three launches (E^H y, then the whole loop),
-  // where a graph launch costs more than it saves (64^2 x 4 coils, 20
-  // iterations: 144 us replayed, 138 us eager), so it always runs eagerly.
+  // A small slice's solve is two launches (the x rows of E^H y, then the
+  // rest of E^H y and the whole loop), where a graph launch costs more than
+  // it saves (measured with one launch more, 64^2 x 4 coils, 20 iterations:
+  // 144 us replayed, 138 us eager), so it always runs eagerly.
   if (!p->graphs || p->profiling || small_solve(p)) {
     hipError_t e = enqueue_solve(p, d_y, x, max_iter, (float)lambda, cg, info2, st);
     return e == hipSuccess ? SENSE_OK : device_fail(e, "sense_cg_solve launch");
