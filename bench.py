@@ -705,7 +705,7 @@ def run_cgsense(args):
     }
     if not args.no_context:
         out["copy_1gib"] = copy_peak(dev)
-        # the same launch against the copy rate measured on this machine
+        # the same launch against the copy rate measured in this run
         out["roofline"]["copy_peak_gbs"] = out["copy_1gib"]["gbs_read_plus_write"]
         out["roofline"]["frac_of_copy"] = achieved / out["copy_1gib"]["gbs_read_plus_write"]
         log(f"bench: 1 GiB copy {out['copy_1gib']['ms']:.3f} ms "
