@@ -74,9 +74,9 @@ def parse():
                     help="cgsense (default, the metric's workload); the others print their own line")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--no-context", action="store_true",
-                    help="skip the context figures (copy peak, torch.fft E^H E, serving summary)")
+                    help="skip the context figures (copy peak, torch.fft E^H E, serving and other workloads)")
     ap.add_argument("--no-serving", action="store_true",
-                    help="skip the serving summary only (profiling runs)")
+                    help="skip the serving and other-workload summaries only (profiling runs)")
     return ap.parse_args()
 
 
@@ -359,14 +359,11 @@ def precision_roofline(st, n, C, B, K, launch_s):
             "achieved_tflops": fl / launch_s / 1e12}
 
 
-def run_precision(args):
-    """384x384, 32 coils, VD R=4, 40 iterations: maps and k-space in c64 /
-    bf16 / fp16 storage (fp32 arithmetic, fp64 reductions), at the workload's
-    batch of 8 slices (whose BF16 working set fits the 256 MB memory-side
-    cache) and at 48 slices (which does not); solves/s, both roofline bounds
-    of the fused CG launch, and the relative L2 difference of each 16-bit
-    result from the GPU complex64 result over all slices.  The errors against
-    the FP64 oracle are the parity test's (tests/test_gpu_precision.py)."""
+def precision_result(batches, storages, reps=5):
+    """Per batch size and storage: seconds per solve, applies/s, the fused CG
+    launch against both bounds, and for 16-bit storage the relative L2
+    difference from the GPU complex64 result (max over slices) and the
+    speed-up over complex64 (storages must start with "c64")."""
     import torch
 
     from paper_1807_11830_amd import sense, synth
@@ -375,7 +372,7 @@ def run_precision(args):
     K, n, C = w.iters, w.n, w.ncoils
     dev = torch.device("cuda:0")
     res = {}
-    for B in (w.batch, 48):
+    for B in batches:
         imgs, maps, mask = synth.slice_inputs(w, B, per_slice_maps=True)
         maps_t = torch.from_numpy(maps.astype(np.complex64)).to(dev)
         imgs_t = torch.from_numpy(imgs.astype(np.complex64)).to(dev)
@@ -387,13 +384,12 @@ def run_precision(args):
         del noise
         out = {}
         xs = {}
-        for st in ("c64", "bf16", "fp16"):
+        for st in storages:
             with sense.Plan(maps_t, mask, batch=B, maps_storage=st, kspace_storage=st) as plan:
                 ys = sense.to_storage(y, st)
                 plan.cg(ys, K)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                reps = 5
                 for _ in range(reps):
                     plan.cg(ys, K, sync=False)
                 torch.cuda.synchronize()
@@ -411,7 +407,7 @@ def run_precision(args):
                 del ys
             log(f"precision: B={B} {st} {dt*1e3:.2f} ms/solve, fused launch {launch_s*1e6:.1f} us, "
                 f"frac {out[st]['fused_launch']['frac']:.3f}")
-        for st in ("bf16", "fp16"):
+        for st in storages[1:]:
             d = xs[st] - xs["c64"]
             out[st]["rel_l2_vs_gpu_c64_max_over_slices"] = float(
                 (torch.linalg.vector_norm(d.reshape(B, -1), dim=1)
@@ -421,19 +417,35 @@ def run_precision(args):
         res[f"batch{B}"] = out
         del maps_t, imgs_t, y, xs
         torch.cuda.empty_cache()
+    return res
+
+
+def run_precision(args):
+    """384x384, 32 coils, VD R=4, 40 iterations: maps and k-space in c64 /
+    bf16 / fp16 storage (fp32 arithmetic, fp64 reductions), at the workload's
+    batch of 8 slices (whose BF16 working set fits the 256 MB memory-side
+    cache) and at 48 slices (which does not); solves/s, both roofline bounds
+    of the fused CG launch, and the relative L2 difference of each 16-bit
+    result from the GPU complex64 result over all slices.  The errors against
+    the FP64 oracle are the parity test's (tests/test_gpu_precision.py)."""
+    from paper_1807_11830_amd import synth
+
+    w = synth.PREC_384
+    K = w.iters
+    res = precision_result((w.batch, 48), ("c64", "bf16", "fp16"))
     print(json.dumps({"metric": "E^H E applies/s by storage precision (CG-SENSE, 40 iterations)",
                       "value": res[f"batch{w.batch}"]["bf16"]["applies_per_s"], "unit": "applies/s", "n_gpus": 1,
                       "higher_is_better": True, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": w.name, "slices": w.batch, "iters": K}, "variants": res}), flush=True)
 
 
-def run_small(args):
-    """One 64x64 slice, 4 coils, 20 CG iterations: the latency of a single
-    solve as the plan runs it by default (two eager launches: the x rows of
-    E^H y, then the rest of E^H y and the whole loop in one workgroup), with
-    graphs switched off (the same launches), and with the coils forced into
-    the workspace's fill split (one fused launch per iteration, replayed
-    from the solve's HIP graph)."""
+def small_result(steps, warmup):
+    """One 64x64 slice, 4 coils, 20 CG iterations: microseconds per solve as
+    the plan runs it by default (two eager launches: the x rows of E^H y,
+    then the rest of E^H y and the whole loop in one workgroup), with graphs
+    switched off (the same launches), and with the coils forced into the
+    workspace's fill split (one fused launch per iteration, replayed from
+    the solve's HIP graph)."""
     import torch
 
     from paper_1807_11830_amd import sense, synth
@@ -451,16 +463,25 @@ def run_small(args):
         for mode in ("default", "graphs_off", f"graph_G{gmax}"):
             plan.set_graphs(mode != "graphs_off")
             plan.set_coil_groups(gmax if mode.endswith(f"_G{gmax}") else gdef)
-            for _ in range(max(args.warmup, 1)):
+            for _ in range(max(warmup, 1)):
                 plan.cg(y, w.iters, out=x, sync=False)
             torch.cuda.synchronize()
-            reps = args.steps
+            reps = steps
             t0 = time.perf_counter()
             for _ in range(reps):
                 plan.cg(y, w.iters, out=x, sync=False)
             torch.cuda.synchronize()
             out[mode] = (time.perf_counter() - t0) / reps * 1e6
             log(f"small: {mode} {out[mode]:.1f} us per solve")
+    return out
+
+
+def run_small(args):
+    """The small-solve latency (small_result) as its own bench line."""
+    from paper_1807_11830_amd import synth
+
+    w = synth.SMALL_64
+    out = small_result(args.steps, args.warmup)
     print(json.dumps({"metric": "CG-SENSE solve latency (64x64, 4 coils, 20 iterations)", "value": out["default"],
                       "unit": "us", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
                       "data": "synthetic", "config": {"workload": w.name},
@@ -508,11 +529,12 @@ def run_paper(args):
                       "results": out}), flush=True)
 
 
-def run_autograd3d(args):
+def autograd3d_result(reps=10):
     """256x256x128 volume, 16 coils, (ky, kz) mask R=6 with a 32x32 centre:
     E forward plus its backward (E^H of a fixed upstream gradient) through
-    torch.autograd, per second; also the whole step of the loss
-    ||E x - y||^2, whose elementwise residual and square run in torch."""
+    torch.autograd; also the whole step of the loss ||E x - y||^2, whose
+    elementwise residual and square run in torch, the pair with compact
+    k-space, and a 10-iteration 3D CG solve."""
     import torch
 
     from paper_1807_11830_amd import sense, synth
@@ -524,7 +546,6 @@ def run_autograd3d(args):
     mask = synth.mask_variable_density_2d(ny, nz, 6.0, (32, 32))
     maps = torch.from_numpy(synth.coil_maps3d(nx, ny, nz, C).astype(np.complex64)).to(dev)
     x_true = torch.from_numpy(synth.phantom3d(nx, ny, nz).astype(np.complex64)[None]).to(dev)
-    reps = 10
     with sense.Plan(maps, mask) as plan:
         y = plan.E(x_true)
         x = torch.zeros_like(x_true, requires_grad=True)
@@ -578,15 +599,24 @@ def run_autograd3d(args):
     log(f"autograd3d: fwd+bwd {dt * 1e3:.2f} ms ({nbytes / dt / 1e9:.0f} GB/s algorithmic), "
         f"loss step {dt_loss * 1e3:.2f} ms, compact k-space fwd+bwd {dt_c * 1e3:.2f} ms "
         f"({nbytes_c / dt_c / 1e9:.0f} GB/s algorithmic)")
+    del maps, x_true, x, g, xs
+    torch.cuda.empty_cache()
+    return {"ms_per_step": dt * 1e3, "algorithmic_bytes": nbytes, "achieved_gbs": nbytes / dt / 1e9,
+            "loss_step_ms": dt_loss * 1e3,
+            "compact_kspace": {"ms_per_step": dt_c * 1e3, "algorithmic_bytes": nbytes_c,
+                               "achieved_gbs": nbytes_c / dt_c / 1e9},
+            "cg3d": {"iters": K, "ms_per_solve": dt_cg * 1e3}}
+
+
+def run_autograd3d(args):
+    """The 3D workload (autograd3d_result) as its own bench line: E forward
+    plus its backward through torch.autograd, per second."""
+    r = autograd3d_result()
+    dt = r.pop("ms_per_step") / 1e3
     print(json.dumps({"metric": "forward+backward of E per second (3D, autograd)", "value": 1.0 / dt,
                       "unit": "fwd+bwd/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
                       "data": "synthetic", "ms_per_step": dt * 1e3,
-                      "config": {"workload": "autograd3d_256x256x128_c16_r6", "coils": C},
-                      "algorithmic_bytes": nbytes, "achieved_gbs": nbytes / dt / 1e9,
-                      "loss_step_ms": dt_loss * 1e3,
-                      "compact_kspace": {"ms_per_step": dt_c * 1e3, "algorithmic_bytes": nbytes_c,
-                                         "achieved_gbs": nbytes_c / dt_c / 1e9},
-                      "cg3d": {"iters": K, "ms_per_solve": dt_cg * 1e3}}), flush=True)
+                      "config": {"workload": "autograd3d_256x256x128_c16_r6", "coils": 16}, **r}), flush=True)
 
 
 def run_cgsense(args):
@@ -726,7 +756,28 @@ def run_cgsense(args):
     torch.cuda.empty_cache()
     if not (args.no_context or args.no_serving):
         out["serving"] = serving_summary()
+        out["other_workloads"] = other_workloads_summary()
     print(json.dumps(out), flush=True)
+
+
+def other_workloads_summary():
+    """Context for the default line: the other configurations at reduced
+    repetition counts (their own --workload lines give the full runs).  A
+    failure here is recorded in the line instead of suppressing it."""
+    from paper_1807_11830_amd import synth
+
+    bp = synth.PREC_384.batch
+    res = {}
+    for name, f in (("small_64x64_c4_k20_us_per_solve", lambda: small_result(100, 5)),
+                    ("precision_384x384_c32_b8_k40", lambda: precision_result((bp,), ("c64", "bf16"), reps=3)[f"batch{bp}"]),
+                    ("autograd3d_256x256x128_c16", lambda: autograd3d_result(reps=5))):
+        t0 = time.perf_counter()
+        try:
+            res[name] = f()
+        except Exception as e:  # context only: the metric's line still prints, with the error
+            res[name] = {"error": f"{type(e).__name__}: {e}"}
+        log(f"bench: {name} in {time.perf_counter() - t0:.1f} s")
+    return res
 
 
 if __name__ == "__main__":
