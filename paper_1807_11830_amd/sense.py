@@ -380,7 +380,7 @@ class Plan:
 def cg_solve_static(maps: torch.Tensor, mask, y: torch.Tensor, x: torch.Tensor, max_iter: int,
                     tol: float = 0.0, lam: float = 0.0, batch: int = 1, maps_storage: str = "c64",
                     kspace_storage: str = "c64", info: torch.Tensor | None = None,
-                    rho_hist: torch.Tensor | None = None, stream=None) -> None:
+                    rho_hist: torch.Tensor | None = None, stream=None, kspace_compact: bool = False) -> None:
     """CG-SENSE of a 2D problem without a plan (sense_cg_solve_static).
 
     The library allocates nothing: its tables and work vectors live in a
@@ -389,8 +389,9 @@ def cg_solve_static(maps: torch.Tensor, mask, y: torch.Tensor, x: torch.Tensor, 
     16-bit pairs with a trailing 2), mask uint8 [Ny] centred, y k-space in
     ``kspace_storage``, x the complex64 [B][Ny][Nx] output; info (optional)
     a device uint8 tensor of 24 * B bytes receiving sense_cg_info per
-    problem, rho_hist (optional) float64 [B][max_iter + 1].  Calls on one
-    GPU must not overlap."""
+    problem, rho_hist (optional) float64 [B][max_iter + 1].  With
+    kspace_compact, y holds the sampled lines only ([B][C][L][Nx]).  Calls
+    on one GPU must not overlap."""
     packed = maps.dtype in (torch.bfloat16, torch.float16)
     mdim = maps.dim() - (1 if packed else 0)
     if mdim == 3:
@@ -412,7 +413,7 @@ def cg_solve_static(maps: torch.Tensor, mask, y: torch.Tensor, x: torch.Tensor, 
     if rho_hist is not None and (rho_hist.dtype != torch.float64 or rho_hist.numel() != batch * (max_iter + 1)):
         raise SenseError(1, "rho_hist must be float64 [B][max_iter + 1]")
     d = Desc(2, int(nx), int(ny), 1, int(ncoils), int(batch), STORAGE[maps_storage], STORAGE[kspace_storage],
-             shared, 0)
+             shared, int(bool(kspace_compact)))
     with torch.cuda.device(x.device):
         _check(lib().sense_cg_solve_static(ctypes.byref(d), _ptr(maps), m.ctypes.data_as(ctypes.c_void_p),
                                            _ptr(y), _ptr(x), int(max_iter), float(tol), float(lam),

@@ -70,6 +70,27 @@ def test_static_solve_matches_plan_twice(first, second):
             assert err_o <= TOL_FP32
 
 
+def test_static_solve_compact_kspace_and_bf16():
+    """Compact k-space (the sampled lines only) in BF16 storage, with BF16
+    maps, on the small-slice path: the static solve against the plan with
+    the same descriptor, bitwise."""
+    w = synth.SMALL_64
+    maps, mask, y = _case(w, 2, seed=synth.SEED_PHANTOM + 11)
+    rows = np.flatnonzero(mask)
+    mq = sense.to_storage(to_dev(maps), "bf16")
+    yq = sense.to_storage(to_dev(y[:, :, rows]).contiguous(), "bf16")
+    x_static = torch.empty((2, w.n, w.n), dtype=torch.complex64, device=DEV)
+    sense.cg_solve_static(mq, mask, yq, x_static, w.iters, batch=2, maps_storage="bf16",
+                          kspace_storage="bf16", kspace_compact=True)
+    torch.cuda.synchronize()
+    with sense.Plan(to_dev(maps), mask, batch=2, maps_storage="bf16", kspace_storage="bf16",
+                    kspace_compact=True) as plan:
+        x_plan = plan.cg(yq, w.iters).x
+        torch.cuda.synchronize()
+    log(f"static compact BF16 vs plan: bitwise {torch.equal(x_static, x_plan)}")
+    assert torch.equal(x_static, x_plan)
+
+
 def test_static_solve_rejects_oversize():
     # 384^2 x 32 coils x 8 slices needs far more than the 64 MiB workspace
     maps = torch.zeros((8, 32, 384, 384), dtype=torch.complex64, device=DEV)
