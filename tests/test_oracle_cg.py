@@ -7,6 +7,8 @@
 * after 64 iterations it equals the least-squares solution of the dense
   system (numpy.linalg.lstsq, a library routine); the A-norm error
   decreases monotonically;
+* with Tikhonov lambda the same two checks hold for A + lambda I (dense
+  numpy.linalg.solve);
 * full sampling with sum |S|^2 = 1 and noise-free data recovers the image in
   one iteration (alpha = 1) — a special case;
 * stop statuses: zero data -> EXACT at 0, tolerance -> CONVERGED,
@@ -83,6 +85,26 @@ def test_cg_converges_to_lstsq_and_error_monotone():
     assert all(e2 <= e1 * (1 + 1e-9) + 1e-13 for e1, e2 in zip(errs, errs[1:]))
     x, iters, status, _ = oracle.cg(y, maps, mask, 64)
     assert np.linalg.norm(x.ravel() - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_cg_with_lambda_solves_the_regularised_system():
+    """With Tikhonov lambda the iterates minimise over the Krylov space of
+    A + lambda I, and 64 iterations give the dense solve of
+    (A + lambda I) x = E^H y (numpy.linalg.solve): a dropped or mis-signed
+    lambda anywhere in the loop fails both."""
+    n, maps, mask, y = _tiny()
+    lam = 0.3
+    Ad = _dense_A(n, maps, mask) + lam * np.eye(n * n)
+    b = oracle.EH(y, maps, mask).ravel()
+    for k in (2, 5):
+        x, _, _, _ = oracle.cg(y, maps, mask, k, lam=lam)
+        ref = _krylov_minimiser(Ad, b, k)
+        assert np.linalg.norm(x.ravel() - ref) <= 1e-9 * np.linalg.norm(ref)
+    x, _, _, _ = oracle.cg(y, maps, mask, 64, lam=lam)
+    xs = np.linalg.solve(Ad, b)
+    assert np.linalg.norm(x.ravel() - xs) <= 1e-9 * np.linalg.norm(xs)
+    x0, _, _, _ = oracle.cg(y, maps, mask, 64)
+    assert np.linalg.norm(x0.ravel() - xs) > 1e-3 * np.linalg.norm(xs)
 
 
 def test_full_sampling_one_iteration_recovery():
