@@ -8,7 +8,7 @@
   system (numpy.linalg.lstsq, a library routine); the A-norm error
   decreases monotonically;
 * with Tikhonov lambda the same two checks hold for A + lambda I (dense
-  numpy.linalg.solve);
+  numpy.linalg.solve), and the Krylov check holds for a tiny volume (3D);
 * full sampling with sum |S|^2 = 1 and noise-free data recovers the image in
   one iteration (alpha = 1) — a special case;
 * stop statuses: zero data -> EXACT at 0, tolerance -> CONVERGED,
@@ -105,6 +105,29 @@ def test_cg_with_lambda_solves_the_regularised_system():
     assert np.linalg.norm(x.ravel() - xs) <= 1e-9 * np.linalg.norm(xs)
     x0, _, _, _ = oracle.cg(y, maps, mask, 64)
     assert np.linalg.norm(x0.ravel() - xs) > 1e-3 * np.linalg.norm(xs)
+
+
+def test_cg_3d_iterates_are_krylov_minimisers():
+    """The same Krylov pin for a tiny volume (4 x 4 x 4, 2 coils, a random
+    (ky, kz) mask; dimension 64): the CG loop at ndim = 3."""
+    nz, ny, nx, nc = 4, 4, 4, 2
+    maps = 0.5 * synth.complex_normal((nc, nz, ny, nx), 80)
+    mask = synth.mask_variable_density_2d(ny, nz, 2.0, (2, 2), seed=81)
+    x_true = synth.complex_normal((1, nz, ny, nx), 82)
+    y = oracle.E(x_true, maps, mask, ndim=3)
+    dim = nx * ny * nz
+    Ad = np.empty((dim, dim), complex)
+    for j in range(dim):
+        e = np.zeros(dim, complex)
+        e[j] = 1.0
+        Ad[:, j] = oracle.A(e.reshape(1, nz, ny, nx), maps, mask, ndim=3).ravel()
+    assert np.allclose(Ad, Ad.conj().T, atol=1e-13)
+    b = oracle.EH(y, maps, mask, ndim=3).ravel()
+    for k in (1, 3, 6):
+        x, iters, status, _ = oracle.cg(y, maps, mask, k, ndim=3)
+        assert iters[0] == k and status[0] == oracle.MAXITER
+        ref = _krylov_minimiser(Ad, b, k)
+        assert np.linalg.norm(x.ravel() - ref) <= 1e-9 * np.linalg.norm(ref)
 
 
 def test_full_sampling_one_iteration_recovery():
